@@ -1,0 +1,137 @@
+"""Python access to the CPU oracle (oracle/bn_oracle.c).
+
+Test infrastructure only: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark may import this module; the product path never does.
+
+Everything is FP64 log-space with full n-bit masks (variable i <-> bit i).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bn_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+BDEU = 0
+K2 = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-o", tmp,
+                        _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.or_local_scores.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_double, P, ctypes.c_int]
+        lib.or_local_scores.restype = ctypes.c_int
+        lib.or_posteriors_from_scores.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P,
+                                                  P, P, ctypes.c_int, ctypes.c_int]
+        lib.or_posteriors_from_scores.restype = ctypes.c_int
+        lib.or_edge_posteriors.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_double, P, P, P, P,
+                                           ctypes.c_int]
+        lib.or_edge_posteriors.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_log_rho(n: int, d: int) -> np.ndarray:
+    """log rho(k) = -log C(n-1, k), k = 0..d."""
+    return np.array([-(math.lgamma(n) - math.lgamma(k + 1) - math.lgamma(n - k))
+                     for k in range(d + 1)], dtype=np.float64)
+
+
+def local_scores(data: np.ndarray, arity, d: int, kind: int = BDEU, ess: float = 1.0,
+                 nthreads: int = 0) -> np.ndarray:
+    """log p(x_i | x_G) as [n, 2^n] (full masks; -inf where G contains i or |G| > d)."""
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    n, m = data.shape
+    ar = np.ascontiguousarray(np.broadcast_to(np.asarray(arity, np.uint8), (n,)))
+    out = np.empty((n, 1 << n), dtype=np.float64)
+    rc = _load().or_local_scores(n, m, _ptr(data), _ptr(ar), min(d, n - 1), kind, ess,
+                                 _ptr(out), nthreads)
+    if rc:
+        raise RuntimeError(f"or_local_scores failed ({rc})")
+    return out
+
+
+def posteriors_from_scores(logB: np.ndarray, d: int, log_q=None, dumps: bool = False,
+                           gamma_free: bool = False, nthreads: int = 0) -> dict:
+    """Steps 2-7 of the method from log B_i(G) given as [n, 2^n] full-mask arrays."""
+    logB = np.ascontiguousarray(logB, dtype=np.float64)
+    n = logB.shape[0]
+    assert logB.shape == (n, 1 << n)
+    lq = None if log_q is None else np.ascontiguousarray(log_q, dtype=np.float64)
+    post = np.zeros((n, n), dtype=np.float64)
+    diag = np.zeros(5, dtype=np.float64)
+    A = F = Rp = Gm = None
+    if dumps:
+        A = np.empty((n, 1 << n)); F = np.empty(1 << n); Rp = np.empty(1 << n)
+        Gm = np.empty((n, 1 << n))
+    rc = _load().or_posteriors_from_scores(n, min(d, n - 1), _ptr(logB), _ptr(lq), _ptr(post),
+                                           _ptr(diag), _ptr(A), _ptr(F), _ptr(Rp), _ptr(Gm),
+                                           1 if gamma_free else 0, nthreads)
+    if rc:
+        raise RuntimeError(f"or_posteriors_from_scores failed ({rc})")
+    res = dict(post=post, log_LV=diag[0], r_LR=diag[1], r_layers=diag[2], r_gamma=diag[3],
+               r_gamma_free=diag[4])
+    if dumps:
+        res.update(alpha=A, L=F, Rp=Rp, gamma=Gm)
+    return res
+
+
+def edge_posteriors(data: np.ndarray, arity, d: int, kind: int = BDEU, ess: float = 1.0,
+                    log_rho=None, log_q=None, nthreads: int = 0) -> dict:
+    """Whole method from data. Returns posteriors [u, v], log L(V), residuals, seconds."""
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    n, m = data.shape
+    ar = np.ascontiguousarray(np.broadcast_to(np.asarray(arity, np.uint8), (n,)))
+    lr = None if log_rho is None else np.ascontiguousarray(log_rho, dtype=np.float64)
+    lq = None if log_q is None else np.ascontiguousarray(log_q, dtype=np.float64)
+    post = np.zeros((n, n), dtype=np.float64)
+    diag = np.zeros(5, dtype=np.float64)
+    t0 = time.perf_counter()
+    rc = _load().or_edge_posteriors(n, m, _ptr(data), _ptr(ar), min(d, n - 1), kind, ess,
+                                    _ptr(lr), _ptr(lq), _ptr(post), _ptr(diag), nthreads)
+    dt = time.perf_counter() - t0
+    if rc:
+        raise RuntimeError(f"or_edge_posteriors failed ({rc})")
+    return dict(post=post, log_LV=diag[0], r_LR=diag[1], r_layers=diag[2], r_gamma=diag[3],
+                seconds=dt)
+
+
+def full_log_beta(data: np.ndarray, arity, d: int, kind: int = BDEU, ess: float = 1.0,
+                  log_rho=None, nthreads: int = 0) -> np.ndarray:
+    """log B_i(G) = log rho(|G|) + log p(x_i|x_G) as [n, 2^n] full-mask arrays."""
+    n = data.shape[0]
+    d = min(d, n - 1)
+    s = local_scores(data, arity, d, kind, ess, nthreads)
+    lr = default_log_rho(n, d) if log_rho is None else np.asarray(log_rho, np.float64)
+    pc = np.array([bin(x).count("1") for x in range(1 << n)])
+    ok = np.isfinite(s)
+    s[ok] += lr[np.broadcast_to(pc, s.shape)[ok]]
+    return s
