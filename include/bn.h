@@ -1,0 +1,176 @@
+/*
+ * bn.h -- C ABI of the MI355X edge-posterior library (libbnpost.so).
+ *
+ * Computes exact posterior probabilities P(u -> v | D) of all n(n-1)
+ * directed edges of a Bayesian network from discrete data, by the
+ * forward-backward dynamic programme over the subset lattice (Algorithm 1,
+ * Sec. 2.2 of Chen, Tian, Nikolova and Aluru, "A Parallel Algorithm for
+ * Exact Bayesian Structure Discovery in Bayesian Networks"):
+ *
+ *   local scores  B_i(G) = rho(|G|) p(x_i | x_G),  |G| <= d        (Eq. 6)
+ *   upward zeta   A_i(S) = q(|S|) sum_{G subset S, |G|<=d} B_i(G)  (Eq. 7)
+ *   forward       F(S)   = sum_{i in S} A_i(S-i) F(S-i)            (Eq. 9)
+ *   backward      R(S), stored prefix-indexed as Rp(S) = R(V-S)    (Eq. 10)
+ *   downward zeta Gamma_v(G) = sum_{G subset S subset V-v}
+ *                               q(|S|) F(S) Rp(S+v),  |G| <= d     (Eq. 12)
+ *   edges         P(u->v|D) = sum_{G containing u} B_v(G) Gamma_v(G) / F(V)
+ *                                                            (Eq. 11)
+ *
+ * Conventions for every call:
+ *   - variable i <-> bit i of a subset mask; data column i = variable i;
+ *   - the caller owns every buffer; the library keeps no caller pointer
+ *     after a call returns (the server copies what it needs at submit);
+ *   - all arguments are validated before any device work; on an error
+ *     nothing is written and no device state changes;
+ *   - on BN_OK every output is complete;
+ *   - the order-modular prior (Eq. 4) is taken to depend on subset size:
+ *     q_i(S) = q(|S|) and rho_i(G) = rho(|G|).
+ */
+#ifndef BN_H
+#define BN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BN_OK = 0,
+    BN_EINVAL = -1,     /* invalid argument (see each call)                        */
+    BN_ENOMEM = -2,     /* the problem's footprint exceeds device memory or budget */
+    BN_EDEVICE = -3,    /* a HIP runtime call failed                               */
+    BN_EAGAIN = -4,     /* serving: result not ready yet                           */
+    BN_ECANCELED = -5,  /* serving: request dropped by bn_server_destroy           */
+    BN_EINTERNAL = -6   /* internal error                                          */
+} bn_status;
+
+typedef enum {
+    BN_FP64_LOG = 0,    /* every lattice value as an FP64 natural logarithm         */
+    BN_FP32_SCALED = 1  /* FP32 significand + 8-bit exponent (units of 2^64) per
+                           entry, on top of exact per-node (B_i) and per-layer (q)
+                           power-of-two scales; FP64 only in the log-gamma score
+                           sums, the scale exponents and the final 1/F(V) step     */
+} bn_precision;
+
+typedef enum {
+    BN_SCORE_BDEU = 0,  /* Dirichlet hyperparameters ess / (q r_i)               */
+    BN_SCORE_K2 = 1     /* all Dirichlet hyperparameters 1                       */
+} bn_score;
+
+/*
+ * The problem statement of Sec. 2.1: discrete data D over n variables with
+ * arities, an in-degree bound d, an order-modular prior and a local score.
+ */
+typedef struct {
+    int32_t n;             /* number of variables, 2..31                             */
+    int32_t m;             /* number of samples, >= 0 (m = 0: every score is 0)      */
+    const uint8_t *data;   /* column-major n*m: data[i*m + s] < arity[i]. Host memory
+                              for bn_local_scores, bn_edge_posteriors and
+                              bn_serve_submit; DEVICE memory for
+                              bn_edge_posteriors_dev                                 */
+    const uint8_t *arity;  /* host, n entries, each 2..255                           */
+    int32_t d;             /* in-degree bound, >= 0; values above n-1 act as n-1     */
+    int32_t score;         /* bn_score                                               */
+    double ess;            /* BDeu equivalent sample size, > 0 (ignored for K2)      */
+    const double *log_rho; /* host or NULL; d+1 values log rho(k), k = 0..min(d,n-1);
+                              NULL: rho(k) = 1 / C(n-1, k)                           */
+    const double *log_q;   /* host or NULL; n values log q(k), k = 0..n-1;
+                              NULL: q == 1                                           */
+} bn_problem;
+
+/* Filled by the solve calls when a non-NULL pointer is passed. */
+typedef struct {
+    double log_LV;                 /* natural log of F(V) = P(D)                     */
+    double max_invariant_residual; /* max over: |log Rp(empty) - log F(V)|,
+                                      |log sum_{|S|=k} F(S)Rp(S) - log F(V)| (all k),
+                                      |log sum_G B_v(G)Gamma_v(G) - log F(V)| (all v) */
+    uint64_t saturated;            /* FP32-scaled: entries clamped at the top of
+                                      the exponent range                             */
+    uint64_t flushed;              /* FP32-scaled: nonzero entries rounded to 0 below
+                                      the bottom of the exponent range               */
+    double ms_scores, ms_alpha, ms_fwd, ms_bwd, ms_gamma, ms_edges, ms_total;
+} bn_report;
+
+/* Number of parent sets of one node: K(n-1, d) = sum_{k<=min(d,n-1)} C(n-1, k).
+ * Returns 0 for n < 1 or d < 0. */
+size_t bn_num_parent_sets(int32_t n, int32_t d);
+
+/*
+ * Local scores (Eq. 6 without the prior factor): log p(x_i | x_G) for every
+ * node i and every G subset V-{i} with |G| <= d.
+ *   log_score: host, n * K(n-1,d) doubles, written as log_score[i*K + r].
+ *   Ranking r of a parent set: G is written as a mask over the n-1 other
+ *   variables in increasing order (bit p <-> variable p if p < i, else p+1);
+ *   r = sum_{k' < |G|} C(n-1, k') + sum_t C(c_t, t), where c_1 < ... < c_|G|
+ *   are the set bit positions (sets by size, then in colex order).
+ * Runs on the current HIP device and blocks until done.
+ * BN_EINVAL: NULL pointers, n out of range, arity out of range, a data value
+ * >= its arity, ess <= 0 (BDeu), d < 0, or a family with more than 2^20
+ * parent-configuration x value bins.
+ */
+bn_status bn_local_scores(const bn_problem *p, double *log_score);
+
+/* Device workspace needed by bn_edge_posteriors_dev for a given problem
+ * shape (m: number of samples). */
+bn_status bn_workspace_bytes(int32_t n, int32_t d, int32_t m, bn_precision prec,
+                             size_t *bytes);
+
+/*
+ * All n(n-1) edge posteriors from host data. Allocates its own device
+ * workspace, copies the data, runs every step on the current HIP device
+ * and blocks until done.
+ *   post: host, n*n doubles, post[u*n + v] = P(u -> v | D); diagonal 0.
+ *   rep:  nullable; per-phase times are measured with HIP events.
+ * BN_EINVAL as for bn_local_scores (and a bad precision); BN_ENOMEM when
+ * the workspace does not fit in device memory.
+ */
+bn_status bn_edge_posteriors(const bn_problem *p, bn_precision prec, double *post,
+                             bn_report *rep);
+
+/*
+ * Same computation with caller-supplied device memory and stream; nothing
+ * is allocated. p->data must point to DEVICE memory (n*m bytes); arity,
+ * log_rho and log_q are host arrays (copied into the workspace).
+ *   dev_ws/ws_bytes: device workspace of at least bn_workspace_bytes().
+ *   hip_stream:      a hipStream_t (NULL: the default stream).
+ *   dev_post:        DEVICE, n*n doubles, written as for bn_edge_posteriors.
+ *   dev_diag:        DEVICE or NULL; 8 doubles: [0] log F(V), [1] max invariant
+ *                    residual, [2] saturated count, [3] flushed count.
+ * Enqueues the work and returns without waiting; the results are valid after
+ * the stream is synchronised. Data values are not range-checked on the host
+ * (they live on the device); out-of-range values give undefined scores but
+ * never out-of-bounds accesses.
+ */
+bn_status bn_edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *dev_ws,
+                                 size_t ws_bytes, void *hip_stream, double *dev_post,
+                                 double *dev_diag);
+
+/*
+ * Serving: a server thread batches solves of mixed n, m and arity as they
+ * arrive (continuous batching). Requests are admitted when their device
+ * footprint fits in mem_budget_bytes (0: 90% of free device memory) and
+ * fewer than max_active are in flight; admitted requests advance phase by
+ * phase, interleaved on several streams.
+ */
+bn_status bn_server_create(size_t mem_budget_bytes, int32_t max_active, void **server);
+/* Copies the problem's inputs; non-blocking. BN_ENOMEM if the request could
+ * never fit in the budget; BN_EINVAL as for bn_edge_posteriors. */
+bn_status bn_serve_submit(void *server, const bn_problem *p, bn_precision prec,
+                          uint64_t *ticket);
+/* Waits up to timeout_us (0: no wait, < 0: forever). BN_OK: post (host n*n)
+ * and rep (nullable) are written and the ticket is released. BN_EAGAIN: not
+ * done yet. BN_ECANCELED: dropped by destroy. BN_EINVAL: unknown ticket. */
+bn_status bn_serve_poll(void *server, uint64_t ticket, double *post, bn_report *rep,
+                        int32_t timeout_us);
+/* Stops the server; pending requests resolve to BN_ECANCELED. */
+bn_status bn_server_destroy(void *server);
+
+const char *bn_status_string(bn_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BN_H */

@@ -1,0 +1,163 @@
+// Device-side numeric policies and subset combinatorics for the lattice kernels.
+//
+// Two number systems share one set of kernels (templates on the policy):
+//
+//  PolLog  -- plain FP64 natural-log values; "add" is log(e^a + e^b),
+//             "mul" is a + b.
+//  PolX32  -- a positive value is f * 2^(64 e): f an FP32 significand kept in
+//             [2^-32, 2^32) after normalisation, e an int. Stored in HBM as an
+//             FP32 word plus one byte b = e + kX32Bias (b = 0 means zero), so
+//             the reach is 2^(64*(1-kX32Bias)) .. 2^(64*(255-kX32Bias)):
+//             about 8,800 nats below the gauge and 2,400 nats above it.
+//             The kernels run on gauged inputs: B_i is divided by an exact
+//             power of two 2^E_i per node and q(k) by 2^F_k per layer. Every
+//             order's weight then changes by the same constant factor
+//             2^(sum E_i + sum F_k), so all posteriors are unchanged.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bnk {
+
+constexpr int kX32Bias = 200;
+constexpr int kEZero = -(1 << 20);   // exponent carried by an exact zero
+
+// ---------------------------------------------------------------- FP64 log
+struct PolLog {
+    using V = double;                 // value in registers and LDS
+    struct Store {                    // value in HBM
+        double *p;
+    };
+    static constexpr int kBytes = 8;
+    __device__ static inline V zero() { return -__builtin_huge_val(); }
+    __device__ static inline V one() { return 0.0; }
+    __device__ static inline V mul(V a, V b) { return a + b; }
+    __device__ static inline V add(V a, V b) {
+        V hi = fmax(a, b), lo = fmin(a, b);
+        if (lo == -__builtin_huge_val()) return hi;
+        return hi + log1p(exp(lo - hi));
+    }
+    __device__ static inline V from_log(double x) { return x; }
+    __device__ static inline double to_log(V v) { return v; }
+    // log(a / b) in FP64, a, b > 0
+    __device__ static inline double log_ratio(V a, V b) { return a - b; }
+    __device__ static inline V load(const Store &s, uint64_t i) { return s.p[i]; }
+    __device__ static inline void store(const Store &s, uint64_t i, V v,
+                                        unsigned long long *) {
+        s.p[i] = v;
+    }
+};
+
+// ------------------------------------------------------- FP32 + exponent
+struct X32 {
+    float f;
+    int e;
+};
+
+struct PolX32 {
+    using V = X32;
+    struct Store {
+        float *f;
+        uint8_t *b;
+    };
+    static constexpr int kBytes = 5;
+    __device__ static inline V zero() { return X32{0.0f, kEZero}; }
+    __device__ static inline V one() { return X32{1.0f, 0}; }
+    // Bring f back into [2^-32, 2^32) (f >= 0, normal or zero).
+    __device__ static inline V norm(V x) {
+        if (!(x.f > 0.0f)) return zero();
+        int bits = __float_as_int(x.f);
+        int k = ((bits >> 23) & 0xff) - 127;
+        int s = (k + 32) >> 6;  // floor((k + 32) / 64)
+        x.f = __int_as_float(bits - (s << 29));
+        x.e += s;
+        return x;
+    }
+    __device__ static inline V mul(V a, V b) { return norm(X32{a.f * b.f, a.e + b.e}); }
+    // Exact alignment to the larger exponent; the smaller operand is scaled
+    // by 2^(-64 * delta) (it underflows to zero only when it is below FP32
+    // resolution of the result).
+    __device__ static inline V add(V a, V b) {
+        int em = max(a.e, b.e);
+        float fa = ldexpf(a.f, (a.e - em) * 64);
+        float fb = ldexpf(b.f, (b.e - em) * 64);
+        return X32{fa + fb, em};
+    }
+    __device__ static inline V from_log(double x) {
+        if (!(x > -1e300)) return zero();
+        double t = x * 1.4426950408889634074;  // log2
+        int e = (int)floor((t + 32.0) / 64.0);
+        float f = (float)exp(x - (double)e * 64.0 * 0.69314718055994530942);
+        return norm(X32{f, e});
+    }
+    __device__ static inline double to_log(V v) {
+        if (!(v.f > 0.0f)) return -__builtin_huge_val();
+        return log((double)v.f) + (double)v.e * 64.0 * 0.69314718055994530942;
+    }
+    __device__ static inline double log_ratio(V a, V b) { return to_log(a) - to_log(b); }
+    __device__ static inline V load(const Store &s, uint64_t i) {
+        uint8_t b = s.b[i];
+        if (b == 0) return zero();
+        return X32{s.f[i], (int)b - kX32Bias};
+    }
+    // cnt[0] counts saturations, cnt[1] flushes of nonzero values.
+    __device__ static inline void store(const Store &s, uint64_t i, V v,
+                                        unsigned long long *cnt) {
+        v = norm(v);
+        int b = v.e + kX32Bias;
+        if (v.f == 0.0f) {
+            s.f[i] = 0.0f;
+            s.b[i] = 0;
+            return;
+        }
+        if (b < 1) {
+            s.f[i] = 0.0f;
+            s.b[i] = 0;
+            if (cnt) atomicAdd(cnt + 1, 1ull);
+            return;
+        }
+        if (b > 255) {
+            s.f[i] = 4.0e9f;
+            s.b[i] = 255;
+            if (cnt) atomicAdd(cnt, 1ull);
+            return;
+        }
+        s.f[i] = v.f;
+        s.b[i] = (uint8_t)b;
+    }
+};
+
+// -------------------------------------------------------- combinatorics
+// binom points at a (33 x 33) table, binom[a * 33 + b] = C(a, b).
+__device__ static inline uint32_t C(const uint32_t *binom, int a, int b) {
+    return (b < 0 || a < 0 || b > a || a > 32) ? 0u : binom[a * 33 + b];
+}
+
+// Number of subsets of a w-set with at most t elements.
+__device__ static inline uint32_t Kcount(const uint32_t *binom, int w, int t) {
+    uint32_t s = 0;
+    for (int k = 0; k <= t && k <= w; ++k) s += C(binom, w, k);
+    return s;
+}
+
+// Positions (ascending) of the colex-rank c subset of size k.
+__device__ static inline void colex_unrank(const uint32_t *binom, uint32_t c, int k,
+                                           int *pos) {
+    for (int t = k; t >= 1; --t) {
+        int p = t - 1;
+        while (p < 31 && C(binom, p + 1, t) <= c) ++p;
+        pos[t - 1] = p;
+        c -= C(binom, p, t);
+    }
+}
+
+// Remove bit i from a mask: the compressed index of S (i not in S) in node
+// i's lattice over the other n-1 variables.
+__device__ static inline uint64_t compress_bit(uint64_t S, int i) {
+    return (S & ((1ull << i) - 1)) | ((S >> (i + 1)) << i);
+}
+__device__ static inline uint64_t expand_bit(uint64_t c, int i) {
+    return (c & ((1ull << i) - 1)) | ((c >> i) << (i + 1));
+}
+
+}  // namespace bnk

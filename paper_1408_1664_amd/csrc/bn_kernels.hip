@@ -1,0 +1,825 @@
+// HIP kernels (gfx950) for the exact edge-posterior programme.
+//
+// Lattice layout in HBM (variable i <-> bit i):
+//   alpha_i : node-major, 2^(n-1) entries per node, indexed by the subset S
+//             of the other n-1 variables with bit i removed (compress_bit).
+//   L, Rp   : 2^n entries indexed by the subset mask.
+//   scores, beta, Gamma : per node, K(n-1,d) parent sets ranked by size then
+//             colex order of the compressed mask.
+//
+// Tiling: a tile is 2^b consecutive masks (the low b bits vary inside a
+// workgroup, the high bits select the tile). Every kernel runs 256 threads.
+#include "bn_device.h"
+#include "bn_kernels.h"
+
+namespace bnk {
+
+constexpr int kThreads = 256;
+
+// ----------------------------------------------------------- block reduce
+// Deterministic tree reduction over the 256 threads of a block (fixed order).
+template <class T, class Op>
+__device__ inline T block_reduce(T v, T *scratch, Op op) {
+    const int t = threadIdx.x;
+    scratch[t] = v;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (t < s) scratch[t] = op(scratch[t], scratch[t + s]);
+        __syncthreads();
+    }
+    T r = scratch[0];
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------------ setup
+// Tables: binomials, popcount-ordered masks of the sweep tile, patterns of
+// at most d ones (numeric order: the w-bit patterns are exactly the first
+// K(w,d) entries), and the ranked seed masks of the Gamma tile.
+__global__ void k_setup(Tables tb, int bL, int W, int bG, int d) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        for (int a = 0; a <= 32; ++a)
+            for (int b = 0; b <= 32; ++b)
+                tb.binom[a * 33 + b] =
+                    (b == 0) ? 1u : (a == 0 ? 0u : tb.binom[(a - 1) * 33 + b - 1] +
+                                                        (b <= a - 1 ? tb.binom[(a - 1) * 33 + b] : 0u));
+    }
+    __syncthreads();
+    const uint32_t *bn = tb.binom;
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (int l = 0; l <= bL; ++l) {
+            tb.loff[l] = acc;
+            acc += C(bn, bL, l);
+        }
+        tb.loff[bL + 1] = acc;
+    }
+    __syncthreads();
+    // popcount-ordered tile masks: position = offset of the layer + colex rank
+    for (uint32_t x = t; x < (1u << bL); x += kThreads) {
+        int k = __popc(x);
+        uint32_t r = 0;
+        int j = 0;
+        for (int p = 0; p < bL; ++p)
+            if ((x >> p) & 1) r += C(bn, p, ++j);
+        tb.lorder[tb.loff[k] + r] = (uint16_t)x;
+    }
+    // patterns with at most d ones over W bits, numeric order
+    for (uint32_t x = t; x < (1u << W); x += kThreads) {
+        int ones = __popc(x);
+        if (ones > d) continue;
+        uint32_t pos = 0;
+        int above = 0;
+        for (int p = W - 1; p >= 0; --p) {
+            if ((x >> p) & 1) {
+                if (d - above >= 0) pos += Kcount(bn, p, d - above);
+                ++above;
+            }
+        }
+        tb.pat[pos] = (uint16_t)x;
+    }
+    // ranked seed masks of the Gamma tile (bG bits): size, then colex
+    for (uint32_t x = t; x < (1u << bG); x += kThreads) {
+        int k = __popc(x);
+        if (k > d) continue;
+        uint32_t r = Kcount(bn, bG, k - 1);
+        int j = 0;
+        for (int p = 0; p < bG; ++p)
+            if ((x >> p) & 1) r += C(bn, p, ++j);
+        tb.seedmask[r] = x;
+    }
+}
+
+// Compressed parent-set masks in rank order, K(N,d) of them.
+__global__ void k_famask(const uint32_t *binom, int N, int d, uint32_t K, uint32_t *famask) {
+    uint32_t r = blockIdx.x * kThreads + threadIdx.x;
+    if (r >= K) return;
+    int k = 0;
+    uint32_t off = 0;
+    while (k < d && r >= off + C(binom, N, k)) off += C(binom, N, k++);
+    int pos[32];
+    colex_unrank(binom, r - off, k, pos);
+    uint32_t msk = 0;
+    for (int t = 0; t < k; ++t) msk |= 1u << pos[t];
+    famask[r] = msk;
+}
+
+// ------------------------------------------------------ a1: local scores
+// One workgroup per family (i, G): integer counts N_jk in an LDS histogram,
+// then the Dirichlet-multinomial log marginal likelihood in FP64.
+__global__ void k_scores(int n, int m, const uint8_t *__restrict__ data,
+                         const uint8_t *__restrict__ arity, uint32_t K, int kind, double ess,
+                         const uint32_t *__restrict__ famask, double *__restrict__ out) {
+    extern __shared__ int hist[];
+    __shared__ double red[kThreads];
+    __shared__ int par[32];
+    __shared__ int npar_s;
+    __shared__ int q_s;
+    const uint32_t fam = blockIdx.x;
+    const int i = fam / K;
+    const uint32_t r = fam % K;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        uint32_t msk = famask[r];
+        int np = 0, q = 1;
+        // mixed radix: the highest variable index is the most significant digit
+        for (int p = 30; p >= 0; --p)
+            if ((msk >> p) & 1) {
+                int var = p < i ? p : p + 1;
+                par[np++] = var;
+                q *= arity[var];
+            }
+        npar_s = np;
+        q_s = q;
+    }
+    __syncthreads();
+    const int np = npar_s, q = q_s, ri = arity[i];
+    const int bins = q * ri;
+    for (int b = t; b < bins; b += kThreads) hist[b] = 0;
+    __syncthreads();
+    const uint8_t *xi = data + (size_t)i * m;
+    for (int s = t; s < m; s += kThreads) {
+        int key = 0;
+        for (int p = 0; p < np; ++p) {
+            int var = par[p];
+            key = key * arity[var] + data[(size_t)var * m + s];
+        }
+        const int bin = key * ri + xi[s];
+        if (bin < bins) atomicAdd(&hist[bin], 1);  // values >= arity are ignored
+    }
+    __syncthreads();
+    double a_j, a_jk;
+    if (kind == 0) {
+        a_j = ess / q;
+        a_jk = ess / ((double)q * ri);
+    } else {
+        a_j = ri;
+        a_jk = 1.0;
+    }
+    const double lg_aj = lgamma(a_j), lg_ajk = lgamma(a_jk);
+    double acc = 0.0;
+    for (int j = t; j < q; j += kThreads) {
+        int nj = 0;
+        double s = 0.0;
+        for (int k = 0; k < ri; ++k) {
+            int c = hist[j * ri + k];
+            if (c) {
+                s += lgamma(a_jk + c) - lg_ajk;
+                nj += c;
+            }
+        }
+        if (nj) acc += s + lg_aj - lgamma(a_j + nj);
+    }
+    double tot = block_reduce(acc, red, [](double a, double b) { return a + b; });
+    if (t == 0) out[fam] = tot;
+}
+
+// ----------------------------------------------- prep: prior and gauges
+// log B_i(G) = log rho(|G|) + log p(x_i|x_G); beta_i = B_i / 2^E_i with
+// E_i = round(max_G log2 B_i(G)) in the scaled form (0 in log form); the same
+// for q(k) with a per-layer exponent F_k.
+template <class P>
+__global__ void k_prep(int n, int d, uint32_t K, const uint32_t *binom,
+                       const double *__restrict__ logp, const double *__restrict__ log_rho,
+                       const double *__restrict__ log_q, int gauge,
+                       typename P::V *__restrict__ beta, typename P::V *__restrict__ qt,
+                       double *__restrict__ gauge_exp) {
+    __shared__ double red[kThreads];
+    const int i = blockIdx.x;
+    const int t = threadIdx.x;
+    const int N = n - 1;
+    double mx = -__builtin_huge_val();
+    for (uint32_t r = t; r < K; r += kThreads) {
+        int k = 0;
+        uint32_t off = 0;
+        while (k < d && r >= off + C(binom, N, k)) off += C(binom, N, k++);
+        mx = fmax(mx, log_rho[k] + logp[(size_t)i * K + r]);
+    }
+    mx = block_reduce(mx, red, [](double a, double b) { return fmax(a, b); });
+    const double E = (gauge && mx > -1e300) ? rint(mx * 1.4426950408889634074) : 0.0;
+    for (uint32_t r = t; r < K; r += kThreads) {
+        int k = 0;
+        uint32_t off = 0;
+        while (k < d && r >= off + C(binom, N, k)) off += C(binom, N, k++);
+        double lb = log_rho[k] + logp[(size_t)i * K + r];
+        beta[(size_t)i * K + r] = P::from_log(lb - E * 0.69314718055994530942);
+    }
+    if (t == 0) gauge_exp[i] = E;
+    if (i == 0) {
+        for (int k = t; k < n; k += kThreads) {
+            double lq = log_q[k];
+            double F = (gauge && lq > -1e300) ? rint(lq * 1.4426950408889634074) : 0.0;
+            qt[k] = P::from_log(lq - F * 0.69314718055994530942);
+            gauge_exp[n + k] = F;
+        }
+    }
+}
+
+// ------------------------------------------------ a2: alpha (upward zeta)
+// Workgroup (i, H): the tile of node i's lattice whose high N-bA bits are H.
+// Seeds Z(G_L) = sum_{G_H subset H, |G_H| <= d-|G_L|} beta_i(G_H + G_L) for
+// every |G_L| <= d, then the truncated upward zeta over the bA low bits
+// (bit j only touches masks with at most d ones above j: the others still
+// hold structural zeros), then alpha = q(|S|) * t(S).
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_alpha(int n, int d, uint32_t K, int bA, Tables tb, const typename P::V *__restrict__ beta,
+        const typename P::V *__restrict__ qt, typename P::Store alpha,
+        unsigned long long *cnt) {
+    using V = typename P::V;
+    extern __shared__ unsigned char smem[];
+    V *tile = reinterpret_cast<V *>(smem);
+    __shared__ int hb[32];
+    __shared__ int h_s;
+    __shared__ V red[kThreads];
+    const int N = n - 1;
+    const int hA = N - bA;
+    const int i = blockIdx.x >> hA;
+    const uint32_t H = blockIdx.x & ((1u << hA) - 1);
+    const int t = threadIdx.x;
+    const uint32_t *bn = tb.binom;
+    if (t == 0) {
+        int h = 0;
+        for (int p = 0; p < hA; ++p)
+            if ((H >> p) & 1) hb[h++] = bA + p;
+        h_s = h;
+    }
+    for (uint32_t x = t; x < (1u << bA); x += kThreads) tile[x] = P::zero();
+    __syncthreads();
+    const int h = h_s;
+    const V *bi = beta + (size_t)i * K;
+    // seeds, one size class s = |G_L| at a time
+    for (int s = 0; s <= d && s <= bA; ++s) {
+        const uint32_t nseed = C(bn, bA, s);
+        const int tt = d - s;                   // max |G_H|
+        const uint32_t items = Kcount(bn, h, tt);
+        int grp = 1;                             // threads per seed (power of 2, <= 64)
+        while (grp < 64 && (uint32_t)(grp * 2) * nseed <= kThreads) grp *= 2;
+        const uint32_t per_round = kThreads / grp;
+        for (uint32_t base = 0; base < nseed; base += per_round) {
+            const uint32_t seed = base + t / grp;
+            const int lane = t % grp;
+            V acc = P::zero();
+            int gl[32];
+            if (seed < nseed) {
+                colex_unrank(bn, seed, s, gl);
+                for (uint32_t it = lane; it < items; it += grp) {
+                    int k = 0;
+                    uint32_t off = 0;
+                    while (k < tt && it >= off + C(bn, h, k)) off += C(bn, h, k++);
+                    int e[32];
+                    colex_unrank(bn, it - off, k, e);
+                    uint32_t rank = Kcount(bn, N, s + k - 1) + seed;
+                    for (int q = 0; q < k; ++q) rank += C(bn, hb[e[q]], s + q + 1);
+                    acc = P::add(acc, bi[rank]);
+                }
+            }
+            // reduce over the grp lanes of each seed (fixed order)
+            red[t] = acc;
+            __syncthreads();
+            for (int w = grp / 2; w > 0; w >>= 1) {
+                if (lane < w) red[t] = P::add(red[t], red[t + w]);
+                __syncthreads();
+            }
+            if (lane == 0 && seed < nseed) {
+                uint32_t msk = 0;
+                for (int q = 0; q < s; ++q) msk |= 1u << gl[q];
+                tile[msk] = red[t];
+            }
+            __syncthreads();
+        }
+    }
+    // truncated upward zeta over the low bA bits
+    for (int j = 0; j < bA; ++j) {
+        const uint32_t np = Kcount(bn, bA - 1 - j, d);
+        const uint32_t cntj = np << j;
+        for (uint32_t idx = t; idx < cntj; idx += kThreads) {
+            uint32_t lo = idx & ((1u << j) - 1);
+            uint32_t p = tb.pat[idx >> j];
+            uint32_t S = (p << (j + 1)) | (1u << j) | lo;
+            tile[S] = P::add(tile[S], tile[S ^ (1u << j)]);
+        }
+        __syncthreads();
+    }
+    const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
+    for (uint32_t x = t; x < (1u << bA); x += kThreads) {
+        int k = h + __popc(x);
+        P::store(alpha, base + x, P::mul(qt[k], tile[x]), cnt);
+    }
+}
+
+// ------------------------------------------- a3: forward sweep, one layer
+// Workgroup = tile H with |H| = h (H over the n-bL high bits). Cross-tile
+// terms (i in H) stream contiguous 2^bL blocks of alpha_i and L; in-tile
+// terms (i among the low bits) use the tile's alpha slices staged in LDS and
+// run popcount layer by popcount layer.
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Store L,
+      unsigned long long *cnt) {
+    using V = typename P::V;
+    extern __shared__ unsigned char smem[];
+    const uint32_t half = 1u << (bL - 1);
+    V *la = reinterpret_cast<V *>(smem);   // bL * half
+    V *lt = la + (size_t)bL * half;        // 2^bL
+    const int t = threadIdx.x;
+    const int nh = n - bL;
+    const uint64_t NN = 1ull << (n - 1);
+    // H: the blockIdx.x-th h-subset of the high bits in colex order
+    int pos[32];
+    colex_unrank(tb.binom, blockIdx.x, h, pos);
+    uint64_t Hf = 0;
+    for (int q = 0; q < h; ++q) Hf |= 1ull << (bL + pos[q]);
+    (void)nh;
+    const uint32_t T = 1u << bL;
+    for (uint32_t lo = t; lo < T; lo += kThreads) {
+        V acc = (Hf == 0 && lo == 0) ? P::one() : P::zero();
+        for (int q = 0; q < h; ++q) {
+            const int i = bL + pos[q];
+            const uint64_t Sm = (Hf ^ (1ull << i)) | lo;
+            acc = P::add(acc, P::mul(P::load(alpha, (uint64_t)i * NN + compress_bit(Sm, i)),
+                                     P::load(L, Sm)));
+        }
+        lt[lo] = acc;
+    }
+    for (int i = 0; i < bL; ++i) {
+        const uint64_t src = (uint64_t)i * NN + (Hf >> 1);
+        for (uint32_t k = t; k < half; k += kThreads) la[i * half + k] = P::load(alpha, src + k);
+    }
+    __syncthreads();
+    for (int l = 1; l <= bL; ++l) {
+        for (uint32_t idx = tb.loff[l] + t; idx < tb.loff[l + 1]; idx += kThreads) {
+            const uint32_t lo = tb.lorder[idx];
+            V acc = lt[lo];
+            uint32_t rest = lo;
+            while (rest) {
+                const int i = __ffs(rest) - 1;
+                rest &= rest - 1;
+                const uint32_t Tm = lo ^ (1u << i);
+                acc = P::add(acc, P::mul(la[i * half + (uint32_t)compress_bit(Tm, i)], lt[Tm]));
+            }
+            lt[lo] = acc;
+        }
+        __syncthreads();
+    }
+    for (uint32_t lo = t; lo < T; lo += kThreads) P::store(L, Hf | lo, lt[lo], cnt);
+}
+
+// ----------------------------------------- a4: backward sweep, one layer
+// Rp(S) = sum_{i not in S} alpha_i(S) Rp(S + i), Rp(V) = 1; layers run from
+// the top. Same tiling as the forward sweep, mirrored.
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Store R,
+      unsigned long long *cnt) {
+    using V = typename P::V;
+    extern __shared__ unsigned char smem[];
+    const uint32_t half = 1u << (bL - 1);
+    V *la = reinterpret_cast<V *>(smem);
+    V *lt = la + (size_t)bL * half;
+    const int t = threadIdx.x;
+    const int nh = n - bL;
+    const uint64_t NN = 1ull << (n - 1);
+    int pos[32];
+    colex_unrank(tb.binom, blockIdx.x, h, pos);
+    uint64_t Hf = 0;
+    for (int q = 0; q < h; ++q) Hf |= 1ull << (bL + pos[q]);
+    const uint64_t highall = ((1ull << nh) - 1) << bL;
+    const uint32_t T = 1u << bL;
+    for (uint32_t lo = t; lo < T; lo += kThreads) {
+        V acc = (Hf == highall && lo == T - 1) ? P::one() : P::zero();
+        const uint64_t Sm = Hf | lo;
+        for (int i = bL; i < n; ++i) {
+            if ((Hf >> i) & 1) continue;
+            acc = P::add(acc, P::mul(P::load(alpha, (uint64_t)i * NN + compress_bit(Sm, i)),
+                                     P::load(R, Sm | (1ull << i))));
+        }
+        lt[lo] = acc;
+    }
+    for (int i = 0; i < bL; ++i) {
+        const uint64_t src = (uint64_t)i * NN + (Hf >> 1);
+        for (uint32_t k = t; k < half; k += kThreads) la[i * half + k] = P::load(alpha, src + k);
+    }
+    __syncthreads();
+    for (int l = bL - 1; l >= 0; --l) {
+        for (uint32_t idx = tb.loff[l] + t; idx < tb.loff[l + 1]; idx += kThreads) {
+            const uint32_t lo = tb.lorder[idx];
+            V acc = lt[lo];
+            uint32_t rest = (T - 1) & ~lo;
+            while (rest) {
+                const int i = __ffs(rest) - 1;
+                rest &= rest - 1;
+                acc = P::add(acc, P::mul(la[i * half + (uint32_t)compress_bit(lo, i)],
+                                         lt[lo | (1u << i)]));
+            }
+            lt[lo] = acc;
+        }
+        __syncthreads();
+    }
+    for (uint32_t lo = t; lo < T; lo += kThreads) P::store(R, Hf | lo, lt[lo], cnt);
+}
+
+// ---------------------------------------- a5 + a6: Gamma, in-tile part
+// Workgroup (v, Hc): tile of v's compressed lattice with high bits Hc.
+// g_v(S) = q(|S|) L(S) Rp(S + v) is formed on the fly, then the truncated
+// downward zeta over the bG low bits (bit j only updates masks with at most
+// d ones among the bits below j: the rest can never reach an output), and
+// the K(bG,d) entries with |G_L| <= d are written to Y1[v][seed][Hc].
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_gamma_tile(int n, int d, int bG, uint32_t KG, Tables tb, typename P::Store L,
+             typename P::Store R, const typename P::V *__restrict__ qt,
+             typename P::V *__restrict__ Y1) {
+    using V = typename P::V;
+    extern __shared__ unsigned char smem[];
+    V *tile = reinterpret_cast<V *>(smem);
+    const int N = n - 1;
+    const int hG = N - bG;
+    const int v = blockIdx.x >> hG;
+    const uint32_t Hc = blockIdx.x & ((1u << hG) - 1);
+    const int t = threadIdx.x;
+    const uint32_t *bn = tb.binom;
+    const uint64_t bv = 1ull << v;
+    for (uint32_t x = t; x < (1u << bG); x += kThreads) {
+        const uint64_t c = ((uint64_t)Hc << bG) | x;
+        const uint64_t S = expand_bit(c, v);
+        tile[x] = P::mul(qt[__popcll(S)], P::mul(P::load(L, S), P::load(R, S | bv)));
+    }
+    __syncthreads();
+    for (int j = 0; j < bG; ++j) {
+        const uint32_t np = Kcount(bn, j, d);
+        const uint32_t cntj = np << (bG - 1 - j);
+        for (uint32_t idx = t; idx < cntj; idx += kThreads) {
+            const uint32_t hi = idx / np;
+            const uint32_t p = tb.pat[idx - hi * np];
+            const uint32_t Tm = (hi << (j + 1)) | p;
+            tile[Tm] = P::add(tile[Tm], tile[Tm | (1u << j)]);
+        }
+        __syncthreads();
+    }
+    const size_t stride = (size_t)1 << hG;
+    for (uint32_t s = t; s < KG; s += kThreads)
+        Y1[((size_t)v * KG + s) * stride + Hc] = tile[tb.seedmask[s]];
+}
+
+// Output rank (within node v's ranked parent sets) of G_L + (high pattern
+// x shifted by shift), |G_L| = sigma with colex rank cl.
+__device__ inline uint32_t out_rank(const uint32_t *bn, int N, int sigma, uint32_t cl,
+                                    uint32_t x, int shift) {
+    int k = 0;
+    uint32_t r = cl;
+    while (x) {
+        const int p = __ffs(x) - 1;
+        x &= x - 1;
+        r += C(bn, shift + p, sigma + (++k));
+    }
+    return Kcount(bn, N, sigma + k - 1) + r;
+}
+
+// ---------------------------------- a6: Gamma, high bits, one level
+// Workgroup (v, seed): the vector Y1[v][seed][.] over the hG high bits;
+// truncated downward zeta keeping |G_H| <= d - |G_L|; writes Gamma_v.
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_gamma_high1(int n, int d, int bG, uint32_t KG, uint32_t K, Tables tb,
+              const typename P::V *__restrict__ Y1, typename P::V *__restrict__ gam) {
+    using V = typename P::V;
+    extern __shared__ unsigned char smem[];
+    V *vec = reinterpret_cast<V *>(smem);
+    const int N = n - 1;
+    const int hG = N - bG;
+    const int v = blockIdx.x / KG;
+    const uint32_t s = blockIdx.x % KG;
+    const int t = threadIdx.x;
+    const uint32_t *bn = tb.binom;
+    const uint32_t gl = tb.seedmask[s];
+    const int sigma = __popc(gl);
+    const int tr = d - sigma;
+    const uint32_t cl = s - Kcount(bn, bG, sigma - 1);
+    const size_t stride = (size_t)1 << hG;
+    const V *src = Y1 + ((size_t)v * KG + s) * stride;
+    for (uint32_t x = t; x < (1u << hG); x += kThreads) vec[x] = src[x];
+    __syncthreads();
+    for (int j = 0; j < hG; ++j) {
+        const uint32_t cntj = Kcount(bn, j, d);  // walk the d-table, skip > tr
+        const uint32_t tot = cntj << (hG - 1 - j);
+        for (uint32_t idx = t; idx < tot; idx += kThreads) {
+            const uint32_t hi = idx / cntj;
+            const uint32_t p = tb.pat[idx - hi * cntj];
+            if (__popc(p) > tr) continue;
+            const uint32_t Tm = (hi << (j + 1)) | p;
+            vec[Tm] = P::add(vec[Tm], vec[Tm | (1u << j)]);
+        }
+        __syncthreads();
+    }
+    const uint32_t npat = Kcount(bn, hG, d);
+    for (uint32_t idx = t; idx < npat; idx += kThreads) {
+        const uint32_t x = tb.pat[idx];
+        if (__popc(x) > tr) continue;
+        gam[(size_t)v * K + out_rank(bn, N, sigma, cl, x, bG)] = vec[x];
+    }
+}
+
+// ------------------------------- a6: Gamma, high bits, two levels (A, B)
+// Level A, workgroup (v, seed, Ht): the low a bits of Hc; output for every
+// a-bit pattern p with at most d ones: Y2[v][seed][p][Ht].
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_gamma_highA(int n, int d, int bG, int a, uint32_t KG, uint32_t KA, Tables tb,
+              const typename P::V *__restrict__ Y1, typename P::V *__restrict__ Y2) {
+    using V = typename P::V;
+    extern __shared__ unsigned char smem[];
+    V *vec = reinterpret_cast<V *>(smem);
+    const int N = n - 1;
+    const int hG = N - bG;
+    const int hB = hG - a;
+    const uint32_t Ht = blockIdx.x & ((1u << hB) - 1);
+    const uint32_t vs = blockIdx.x >> hB;     // v * KG + seed
+    const uint32_t s = vs % KG;
+    const int t = threadIdx.x;
+    const uint32_t *bn = tb.binom;
+    const int tr = d - __popc(tb.seedmask[s]);
+    const V *src = Y1 + ((size_t)vs << hG) + ((size_t)Ht << a);
+    for (uint32_t x = t; x < (1u << a); x += kThreads) vec[x] = src[x];
+    __syncthreads();
+    for (int j = 0; j < a; ++j) {
+        const uint32_t cntj = Kcount(bn, j, d);
+        const uint32_t tot = cntj << (a - 1 - j);
+        for (uint32_t idx = t; idx < tot; idx += kThreads) {
+            const uint32_t hi = idx / cntj;
+            const uint32_t p = tb.pat[idx - hi * cntj];
+            if (__popc(p) > tr) continue;
+            const uint32_t Tm = (hi << (j + 1)) | p;
+            vec[Tm] = P::add(vec[Tm], vec[Tm | (1u << j)]);
+        }
+        __syncthreads();
+    }
+    for (uint32_t pi = t; pi < KA; pi += kThreads) {
+        const uint32_t x = tb.pat[pi];
+        Y2[(((size_t)vs * KA + pi) << hB) + Ht] = vec[x];
+    }
+}
+
+// Level B, workgroup (v, seed): for each a-bit pattern p and each output
+// pattern y over the remaining hB bits, the superset sum over y' of y.
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_gamma_highB(int n, int d, int bG, int a, uint32_t KG, uint32_t KA, uint32_t K, Tables tb,
+              const typename P::V *__restrict__ Y2, typename P::V *__restrict__ gam) {
+    using V = typename P::V;
+    const int N = n - 1;
+    const int hG = N - bG;
+    const int hB = hG - a;
+    const uint32_t vs = blockIdx.x;
+    const int v = vs / KG;
+    const uint32_t s = vs % KG;
+    const int t = threadIdx.x;
+    const uint32_t *bn = tb.binom;
+    const uint32_t gl = tb.seedmask[s];
+    const int sigma = __popc(gl);
+    const int tr = d - sigma;
+    const uint32_t cl = s - Kcount(bn, bG, sigma - 1);
+    const uint32_t ny = 1u << hB;
+    for (uint32_t idx = t; idx < KA * ny; idx += kThreads) {
+        const uint32_t pi = idx / ny;
+        const uint32_t y = idx - pi * ny;
+        const uint32_t p = tb.pat[pi];
+        if (__popc(p) + __popc(y) > tr) continue;
+        const V *src = Y2 + (((size_t)vs * KA + pi) << hB);
+        V acc = P::zero();
+        const uint32_t free_bits = (ny - 1) & ~y;
+        // all supersets y' = y | sub, sub subset of free_bits, ascending
+        uint32_t sub = 0;
+        while (true) {
+            acc = P::add(acc, src[y | sub]);
+            if (sub == free_bits) break;
+            sub = (sub - free_bits) & free_bits;
+        }
+        const uint32_t x = p | (y << a);
+        gam[(size_t)v * K + out_rank(bn, N, sigma, cl, x, bG)] = acc;
+    }
+}
+
+// ------------------------------------------------------------ a7: edges
+// Workgroup v: w_v(G) = beta_v(G) Gamma_v(G); P(u->v) = sum_{G containing u}
+// w_v(G) / L(V), the last division in FP64. Also sum_G w_v(G) against L(V).
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_edges(int n, uint32_t K, const uint32_t *__restrict__ famask,
+        const typename P::V *__restrict__ beta, const typename P::V *__restrict__ gam,
+        typename P::Store L, double *__restrict__ post, double *__restrict__ resid) {
+    using V = typename P::V;
+    __shared__ V red[kThreads];
+    const int v = blockIdx.x;
+    const int t = threadIdx.x;
+    const V LV = P::load(L, (1ull << n) - 1);
+    auto add = [](V a, V b) { return P::add(a, b); };
+    for (int u = -1; u < n; ++u) {
+        if (u == v) {
+            if (t == 0) post[(size_t)u * n + v] = 0.0;
+            continue;
+        }
+        const int pu = u < v ? u : u - 1;
+        V acc = P::zero();
+        for (uint32_t r = t; r < K; r += kThreads) {
+            if (u >= 0 && !((famask[r] >> pu) & 1)) continue;
+            acc = P::add(acc, P::mul(beta[(size_t)v * K + r], gam[(size_t)v * K + r]));
+        }
+        V tot = block_reduce(acc, red, add);
+        if (t == 0) {
+            double lr = P::log_ratio(tot, LV);
+            if (u < 0) resid[v] = fabs(lr);
+            else post[(size_t)u * n + v] = (lr > -1e300) ? exp(lr) : 0.0;
+        }
+    }
+}
+
+// -------------------------------------------------------- invariants
+// Per tile H and in-tile layer l: sum of L(S) Rp(S); then per layer k of
+// the whole lattice. Every layer sum must equal L(V).
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_inv1(int n, int bL, Tables tb, typename P::Store L, typename P::Store R,
+       typename P::V *__restrict__ part) {
+    using V = typename P::V;
+    __shared__ V red[kThreads];
+    const uint64_t Hf = (uint64_t)blockIdx.x << bL;
+    const int t = threadIdx.x;
+    auto add = [](V a, V b) { return P::add(a, b); };
+    for (int l = 0; l <= bL; ++l) {
+        V acc = P::zero();
+        for (uint32_t idx = tb.loff[l] + t; idx < tb.loff[l + 1]; idx += kThreads) {
+            const uint64_t S = Hf | tb.lorder[idx];
+            acc = P::add(acc, P::mul(P::load(L, S), P::load(R, S)));
+        }
+        V s = block_reduce(acc, red, add);
+        if (t == 0) part[(size_t)blockIdx.x * (bL + 1) + l] = s;
+    }
+}
+
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_inv2(int n, int bL, const typename P::V *__restrict__ part, typename P::V *__restrict__ layer) {
+    using V = typename P::V;
+    __shared__ V red[kThreads];
+    const int k = blockIdx.x;
+    const int t = threadIdx.x;
+    const uint32_t ntile = 1u << (n - bL);
+    auto add = [](V a, V b) { return P::add(a, b); };
+    V acc = P::zero();
+    for (uint32_t H = t; H < ntile; H += kThreads) {
+        const int l = k - __popc(H);
+        if (l < 0 || l > bL) continue;
+        acc = P::add(acc, part[(size_t)H * (bL + 1) + l]);
+    }
+    V s = block_reduce(acc, red, add);
+    if (t == 0) layer[k] = s;
+}
+
+// diag: [0] log L(V), [1] max residual, [2] saturated, [3] flushed,
+//       [4] |log Rp(0) - log L(V)|, [5] max layer residual, [6] max edge-sum residual
+template <class P>
+__global__ void k_finalize(int n, typename P::Store L, typename P::Store R,
+                           const typename P::V *__restrict__ layer,
+                           const double *__restrict__ resid, const double *__restrict__ gauge_exp,
+                           const unsigned long long *__restrict__ cnt, double *__restrict__ diag) {
+    if (threadIdx.x != 0) return;
+    using V = typename P::V;
+    const V LV = P::load(L, (1ull << n) - 1);
+    double g = 0.0;
+    for (int k = 0; k < 2 * n; ++k) g += gauge_exp[k];
+    const double rLR = fabs(P::log_ratio(P::load(R, 0), LV));
+    double rl = 0.0;
+    for (int k = 0; k <= n; ++k) rl = fmax(rl, fabs(P::log_ratio(layer[k], LV)));
+    double re = 0.0;
+    for (int v = 0; v < n; ++v) re = fmax(re, resid[v]);
+    diag[0] = P::to_log(LV) + g * 0.69314718055994530942;
+    diag[1] = fmax(rLR, fmax(rl, re));
+    diag[2] = (double)cnt[0];
+    diag[3] = (double)cnt[1];
+    diag[4] = rLR;
+    diag[5] = rl;
+    diag[6] = re;
+}
+
+// -------------------------------------------------------------- launchers
+#define BN_CHECK_LAUNCH() \
+    do {                                                   \
+        hipError_t e_ = hipGetLastError();                 \
+        if (e_ != hipSuccess) return e_;                   \
+    } while (0)
+
+hipError_t launch_setup(const Tables &tb, int bL, int W, int bG, int d, uint32_t N, uint32_t K,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(kThreads), 0, st, tb, bL, W, bG, d);
+    BN_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_famask, dim3((K + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
+                       (const uint32_t *)tb.binom, (int)N, d, K, tb.famask);
+    BN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_scores(int n, int m, const uint8_t *data, const uint8_t *arity, uint32_t K,
+                         int kind, double ess, const uint32_t *famask, int max_bins,
+                         double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_scores, dim3((unsigned)(n * K)), dim3(kThreads),
+                       (size_t)max_bins * sizeof(int), st, n, m, data, arity, K, kind, ess,
+                       famask, out);
+    BN_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <class P>
+hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
+                          const typename P::Store &L, const typename P::Store &R,
+                          hipStream_t st, PhaseEvents *ev) {
+    using V = typename P::V;
+    const int n = a.n, N = n - 1, d = a.d;
+    const Tables &tb = a.tb;
+    V *beta = reinterpret_cast<V *>(a.beta);
+    V *qt = reinterpret_cast<V *>(a.qt);
+    V *Y1 = reinterpret_cast<V *>(a.Y1);
+    V *Y2 = reinterpret_cast<V *>(a.Y2);
+    V *gam = reinterpret_cast<V *>(a.gam);
+    V *part = reinterpret_cast<V *>(a.part);
+    V *layer = reinterpret_cast<V *>(a.layer);
+    auto rec = [&](int idx) {
+        if (ev && ev->ev[idx]) (void)hipEventRecord(ev->ev[idx], st);
+    };
+    hipLaunchKernelGGL(k_prep<P>, dim3(n), dim3(kThreads), 0, st, n, d, a.K,
+                       (const uint32_t *)tb.binom, (const double *)a.logp,
+                       (const double *)a.log_rho, (const double *)a.log_q, a.gauge, beta, qt,
+                       a.gauge_exp);
+    BN_CHECK_LAUNCH();
+    rec(1);
+    {
+        const size_t sm = sizeof(V) << a.bA;
+        hipLaunchKernelGGL(k_alpha<P>, dim3((unsigned)(n << (N - a.bA))), dim3(kThreads), sm, st,
+                           n, d, a.K, a.bA, tb, (const V *)beta, (const V *)qt, alpha, a.cnt);
+        BN_CHECK_LAUNCH();
+    }
+    rec(2);
+    const int nh = n - a.bL;
+    const size_t smL = sizeof(V) * (((size_t)a.bL << (a.bL - 1)) + ((size_t)1 << a.bL));
+    for (int h = 0; h <= nh; ++h) {
+        const unsigned nb = a.tiles_per_layer[h];
+        hipLaunchKernelGGL(k_fwd<P>, dim3(nb), dim3(kThreads), smL, st, n, a.bL, h, tb, alpha, L,
+                           a.cnt);
+        BN_CHECK_LAUNCH();
+    }
+    rec(3);
+    for (int h = nh; h >= 0; --h) {
+        const unsigned nb = a.tiles_per_layer[h];
+        hipLaunchKernelGGL(k_bwd<P>, dim3(nb), dim3(kThreads), smL, st, n, a.bL, h, tb, alpha, R,
+                           a.cnt);
+        BN_CHECK_LAUNCH();
+    }
+    rec(4);
+    {
+        const int hG = N - a.bG;
+        hipLaunchKernelGGL(k_gamma_tile<P>, dim3((unsigned)(n << hG)), dim3(kThreads),
+                           sizeof(V) << a.bG, st, n, d, a.bG, a.KG, tb, L, R, (const V *)qt, Y1);
+        BN_CHECK_LAUNCH();
+        if (hG <= a.aG) {
+            hipLaunchKernelGGL(k_gamma_high1<P>, dim3((unsigned)(n * a.KG)), dim3(kThreads),
+                               sizeof(V) << hG, st, n, d, a.bG, a.KG, a.K, tb, (const V *)Y1,
+                               gam);
+            BN_CHECK_LAUNCH();
+        } else {
+            const int hB = hG - a.aG;
+            hipLaunchKernelGGL(k_gamma_highA<P>, dim3((unsigned)((n * a.KG) << hB)),
+                               dim3(kThreads), sizeof(V) << a.aG, st, n, d, a.bG, a.aG, a.KG,
+                               a.KA, tb, (const V *)Y1, Y2);
+            BN_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_gamma_highB<P>, dim3((unsigned)(n * a.KG)), dim3(kThreads), 0,
+                               st, n, d, a.bG, a.aG, a.KG, a.KA, a.K, tb, (const V *)Y2, gam);
+            BN_CHECK_LAUNCH();
+        }
+    }
+    rec(5);
+    hipLaunchKernelGGL(k_edges<P>, dim3(n), dim3(kThreads), 0, st, n, a.K,
+                       (const uint32_t *)tb.famask, (const V *)beta, (const V *)gam, L, a.post,
+                       a.resid);
+    BN_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_inv1<P>, dim3(1u << nh), dim3(kThreads), 0, st, n, a.bL, tb, L, R, part);
+    BN_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_inv2<P>, dim3(n + 1), dim3(kThreads), 0, st, n, a.bL, (const V *)part,
+                       layer);
+    BN_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_finalize<P>, dim3(1), dim3(64), 0, st, n, L, R, (const V *)layer,
+                       (const double *)a.resid, (const double *)a.gauge_exp,
+                       (const unsigned long long *)a.cnt, a.diag);
+    BN_CHECK_LAUNCH();
+    rec(6);
+    return hipSuccess;
+}
+
+template hipError_t launch_lattice<PolLog>(const LatticeArgs &, const PolLog::Store &,
+                                           const PolLog::Store &, const PolLog::Store &,
+                                           hipStream_t, PhaseEvents *);
+template hipError_t launch_lattice<PolX32>(const LatticeArgs &, const PolX32::Store &,
+                                           const PolX32::Store &, const PolX32::Store &,
+                                           hipStream_t, PhaseEvents *);
+
+}  // namespace bnk

@@ -1,0 +1,437 @@
+// Host side of the library: problem validation, the plan (tile sizes and
+// workspace layout), the launch sequence and the C ABI of bn.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "../../include/bn.h"
+#include "bn_device.h"
+#include "bn_kernels.h"
+#include "bn_solver.h"
+
+namespace bnk {
+
+static uint64_t binom_u64(int a, int b) {
+    if (b < 0 || b > a) return 0;
+    uint64_t r = 1;
+    for (int k = 1; k <= b; ++k) r = r * (uint64_t)(a - b + k) / (uint64_t)k;
+    return r;
+}
+static uint64_t kcount_u64(int w, int t) {
+    uint64_t s = 0;
+    for (int k = 0; k <= t && k <= w; ++k) s += binom_u64(w, k);
+    return s;
+}
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Parameters passed by value to the parameter kernel (host arrays are
+// consumed at launch, so no caller pointer is kept).
+struct ParamBlock {
+    uint8_t arity[32];
+    double log_rho[33];
+    double log_q[32];
+    int has_rho, has_q;
+};
+
+__global__ void k_params(ParamBlock pb, int n, int d, uint8_t *arity, double *log_rho,
+                         double *log_q, unsigned long long *cnt) {
+    const int t = threadIdx.x;
+    if (t < n) {
+        arity[t] = pb.arity[t];
+        log_q[t] = pb.has_q ? pb.log_q[t] : 0.0;
+    }
+    if (t <= d) {
+        // default rho(k) = 1 / C(n-1, k)
+        log_rho[t] = pb.has_rho ? pb.log_rho[t]
+                                : -(lgamma((double)n) - lgamma((double)t + 1.0) -
+                                    lgamma((double)(n - t)));
+    }
+    if (t < 2) cnt[t] = 0ull;
+}
+
+bn_status validate(const bn_problem *p, bool host_data, bool check_values) {
+    if (!p) return BN_EINVAL;
+    if (p->n < 2 || p->n > 31) return BN_EINVAL;
+    if (p->m < 0) return BN_EINVAL;
+    if (p->d < 0) return BN_EINVAL;
+    if (p->score != BN_SCORE_BDEU && p->score != BN_SCORE_K2) return BN_EINVAL;
+    if (p->score == BN_SCORE_BDEU && !(p->ess > 0.0 && std::isfinite(p->ess))) return BN_EINVAL;
+    if (!p->arity) return BN_EINVAL;
+    if (p->m > 0 && !p->data) return BN_EINVAL;
+    const int n = p->n;
+    const int d = std::min(p->d, n - 1);
+    for (int i = 0; i < n; ++i)
+        if (p->arity[i] < 2) return BN_EINVAL;
+    if (p->log_rho)
+        for (int k = 0; k <= d; ++k)
+            if (std::isnan(p->log_rho[k]) || p->log_rho[k] == HUGE_VAL) return BN_EINVAL;
+    if (p->log_q)
+        for (int k = 0; k < n; ++k)
+            if (std::isnan(p->log_q[k]) || p->log_q[k] == HUGE_VAL) return BN_EINVAL;
+    // one workgroup per family must fit one grid dimension
+    if ((double)n * (double)kcount_u64(n - 1, d) > 2147483647.0) return BN_EINVAL;
+    // histogram bins of the largest family of each node
+    for (int i = 0; i < n; ++i) {
+        std::vector<int> ar;
+        for (int j = 0; j < n; ++j)
+            if (j != i) ar.push_back(p->arity[j]);
+        std::sort(ar.rbegin(), ar.rend());
+        double bins = p->arity[i];
+        for (int k = 0; k < d; ++k) bins *= ar[k];
+        if (bins > kMaxBins) return BN_EINVAL;
+    }
+    if (host_data && check_values && p->m > 0) {
+        for (int i = 0; i < n; ++i) {
+            const uint8_t *col = p->data + (size_t)i * p->m;
+            const uint8_t r = p->arity[i];
+            for (int s = 0; s < p->m; ++s)
+                if (col[s] >= r) return BN_EINVAL;
+        }
+    }
+    return BN_OK;
+}
+
+Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool with_post) {
+    Plan P{};
+    P.n = n;
+    P.m = m;
+    P.d = std::min(d_in, n - 1);
+    P.N = n - 1;
+    P.x32 = (prec == BN_FP32_SCALED);
+    const int N = P.N, d = P.d;
+    P.K = (uint32_t)kcount_u64(N, d);
+    P.bA = std::min(N, 12);
+    P.bL = std::min(n, 10);
+    P.bG = std::min(N, 12);
+    P.aG = 12;
+    // Tuning / test override "bA,bL,bG,aG" (each clamped to its valid range);
+    // lets small problems exercise every tiling path.
+    if (const char *tb = getenv("BN_TILE_BITS")) {
+        int v[4] = {P.bA, P.bL, P.bG, P.aG};
+        if (sscanf(tb, "%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3]) == 4) {
+            P.bA = std::max(1, std::min(v[0], N));
+            P.bL = std::max(1, std::min(v[1], n));
+            P.bG = std::max(1, std::min(v[2], N));
+            P.aG = std::max(1, std::min(v[3], 12));
+        }
+    }
+    const int hG = N - P.bG;
+    P.two_level = hG > P.aG;
+    P.KG = (uint32_t)kcount_u64(P.bG, d);
+    P.KA = P.two_level ? (uint32_t)kcount_u64(P.aG, d) : 0;
+    P.W = std::max(std::max(P.bA, P.bG), P.two_level ? P.aG : hG);
+    P.W = std::max(P.W, 1);
+    const int nh = n - P.bL;
+    P.tiles.resize(nh + 1);
+    for (int h = 0; h <= nh; ++h) P.tiles[h] = (uint32_t)binom_u64(nh, h);
+
+    const uint64_t NN = 1ull << N, NS = 1ull << n;
+    const size_t V = 8;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += align256(bytes);
+        return r;
+    };
+    P.o_binom = take(33 * 33 * 4);
+    P.o_lorder = take(((size_t)1 << P.bL) * 2);
+    P.o_loff = take((P.bL + 2) * 4);
+    P.o_pat = take(((size_t)1 << P.W) * 2);
+    P.o_seed = take(P.KG * 4);
+    P.o_famask = take((size_t)P.K * 4);
+    P.o_arity = take(64);
+    P.o_rho = take(34 * 8);
+    P.o_q = take(32 * 8);
+    P.o_logp = take((size_t)n * P.K * 8);
+    P.o_beta = take((size_t)n * P.K * V);
+    P.o_qt = take(32 * V);
+    P.o_gexp = take(64 * 8);
+    if (P.x32) {
+        P.o_alpha_f = take((size_t)n * NN * 4);
+        P.o_alpha_b = take((size_t)n * NN);
+        P.o_L_f = take(NS * 4);
+        P.o_L_b = take(NS);
+        P.o_R_f = take(NS * 4);
+        P.o_R_b = take(NS);
+    } else {
+        P.o_alpha_f = take((size_t)n * NN * 8);
+        P.o_L_f = take(NS * 8);
+        P.o_R_f = take(NS * 8);
+    }
+    P.o_Y1 = take((size_t)n * P.KG * ((size_t)1 << hG) * V);
+    if (P.two_level)
+        P.o_Y2 = take((size_t)n * P.KG * P.KA * ((size_t)1 << (hG - P.aG)) * V);
+    P.o_gam = take((size_t)n * P.K * V);
+    P.o_part = take(((size_t)1 << nh) * (P.bL + 1) * V);
+    P.o_layer = take(33 * V);
+    P.o_resid = take(32 * 8);
+    P.o_diag = take(16 * 8);
+    P.o_cnt = take(4 * 8);
+    if (with_post) P.o_post = take((size_t)n * n * 8);
+    if (with_data) P.o_data = take((size_t)n * (size_t)std::max(m, 1));
+    P.total = o;
+    P.max_bins = 1;
+    return P;
+}
+
+static int max_bins_of(const bn_problem *p, int d) {
+    int best = 1;
+    for (int i = 0; i < p->n; ++i) {
+        std::vector<int> ar;
+        for (int j = 0; j < p->n; ++j)
+            if (j != i) ar.push_back(p->arity[j]);
+        std::sort(ar.rbegin(), ar.rend());
+        long bins = p->arity[i];
+        for (int k = 0; k < d; ++k) bins *= ar[k];
+        best = (int)std::max<long>(best, bins);
+    }
+    return best;
+}
+
+static Tables tables_of(const Plan &P, char *ws) {
+    Tables tb;
+    tb.binom = reinterpret_cast<uint32_t *>(ws + P.o_binom);
+    tb.lorder = reinterpret_cast<uint16_t *>(ws + P.o_lorder);
+    tb.loff = reinterpret_cast<uint32_t *>(ws + P.o_loff);
+    tb.pat = reinterpret_cast<uint16_t *>(ws + P.o_pat);
+    tb.seedmask = reinterpret_cast<uint32_t *>(ws + P.o_seed);
+    tb.famask = reinterpret_cast<uint32_t *>(ws + P.o_famask);
+    return tb;
+}
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        hipError_t e__ = (x);                       \
+        if (e__ != hipSuccess) return BN_EDEVICE;   \
+    } while (0)
+
+// Enqueue parameters, tables and local scores on stream st.
+static bn_status enqueue_scores(const Plan &P, const bn_problem *p, const uint8_t *dev_data,
+                                char *ws, hipStream_t st) {
+    ParamBlock pb{};
+    for (int i = 0; i < P.n; ++i) pb.arity[i] = p->arity[i];
+    pb.has_rho = p->log_rho != nullptr;
+    pb.has_q = p->log_q != nullptr;
+    if (p->log_rho)
+        for (int k = 0; k <= P.d; ++k) pb.log_rho[k] = p->log_rho[k];
+    if (p->log_q)
+        for (int k = 0; k < P.n; ++k) pb.log_q[k] = p->log_q[k];
+    auto *cnt = reinterpret_cast<unsigned long long *>(ws + P.o_cnt);
+    hipLaunchKernelGGL(k_params, dim3(1), dim3(64), 0, st, pb, P.n, P.d,
+                       reinterpret_cast<uint8_t *>(ws + P.o_arity),
+                       reinterpret_cast<double *>(ws + P.o_rho),
+                       reinterpret_cast<double *>(ws + P.o_q), cnt);
+    HIPCHK(hipGetLastError());
+    Tables tb = tables_of(P, ws);
+    HIPCHK(launch_setup(tb, P.bL, P.W, P.bG, P.d, P.N, P.K, st));
+    const int kind = p->score == BN_SCORE_K2 ? 1 : 0;
+    HIPCHK(launch_scores(P.n, P.m, dev_data, reinterpret_cast<const uint8_t *>(ws + P.o_arity), P.K,
+                         kind, p->ess, tb.famask, max_bins_of(p, P.d),
+                         reinterpret_cast<double *>(ws + P.o_logp), st));
+    return BN_OK;
+}
+
+bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_data, char *ws,
+                        hipStream_t st, double *dev_post, double *dev_diag, PhaseEvents *ev) {
+    if (ev && ev->ev[0]) HIPCHK(hipEventRecord(ev->ev[0], st));
+    bn_status s = enqueue_scores(P, p, dev_data, ws, st);
+    if (s != BN_OK) return s;
+    LatticeArgs a{};
+    a.n = P.n;
+    a.d = P.d;
+    a.K = P.K;
+    a.bA = P.bA;
+    a.bL = P.bL;
+    a.bG = P.bG;
+    a.aG = P.aG;
+    a.KG = P.KG;
+    a.KA = P.KA;
+    a.gauge = P.x32 ? 1 : 0;
+    a.tb = tables_of(P, ws);
+    a.logp = reinterpret_cast<const double *>(ws + P.o_logp);
+    a.log_rho = reinterpret_cast<const double *>(ws + P.o_rho);
+    a.log_q = reinterpret_cast<const double *>(ws + P.o_q);
+    a.beta = ws + P.o_beta;
+    a.qt = ws + P.o_qt;
+    a.Y1 = ws + P.o_Y1;
+    a.Y2 = P.two_level ? ws + P.o_Y2 : nullptr;
+    a.gam = ws + P.o_gam;
+    a.part = ws + P.o_part;
+    a.layer = ws + P.o_layer;
+    a.gauge_exp = reinterpret_cast<double *>(ws + P.o_gexp);
+    a.post = dev_post;
+    a.resid = reinterpret_cast<double *>(ws + P.o_resid);
+    a.diag = dev_diag ? dev_diag : reinterpret_cast<double *>(ws + P.o_diag);
+    a.cnt = reinterpret_cast<unsigned long long *>(ws + P.o_cnt);
+    a.tiles_per_layer = P.tiles.data();
+    hipError_t e;
+    if (P.x32) {
+        PolX32::Store al{reinterpret_cast<float *>(ws + P.o_alpha_f),
+                         reinterpret_cast<uint8_t *>(ws + P.o_alpha_b)};
+        PolX32::Store L{reinterpret_cast<float *>(ws + P.o_L_f),
+                        reinterpret_cast<uint8_t *>(ws + P.o_L_b)};
+        PolX32::Store R{reinterpret_cast<float *>(ws + P.o_R_f),
+                        reinterpret_cast<uint8_t *>(ws + P.o_R_b)};
+        e = launch_lattice<PolX32>(a, al, L, R, st, ev);
+    } else {
+        PolLog::Store al{reinterpret_cast<double *>(ws + P.o_alpha_f)};
+        PolLog::Store L{reinterpret_cast<double *>(ws + P.o_L_f)};
+        PolLog::Store R{reinterpret_cast<double *>(ws + P.o_R_f)};
+        e = launch_lattice<PolLog>(a, al, L, R, st, ev);
+    }
+    return e == hipSuccess ? BN_OK : BN_EDEVICE;
+}
+
+bn_status local_scores_host(const bn_problem *p, double *log_score) {
+    bn_status s = validate(p, true, true);
+    if (s != BN_OK) return s;
+    if (!log_score) return BN_EINVAL;
+    Plan P = make_plan(p->n, p->d, p->m, BN_FP64_LOG, true, false);
+    // only the tables, parameters, scores and data are needed
+    size_t need = std::max(P.o_logp + align256((size_t)P.n * P.K * 8), (size_t)0);
+    (void)need;
+    char *ws = nullptr;
+    size_t small = P.o_beta;  // everything before beta
+    size_t data_bytes = (size_t)P.n * std::max(P.m, 1);
+    if (hipMalloc(&ws, small + align256(data_bytes)) != hipSuccess) return BN_ENOMEM;
+    uint8_t *dev_data = reinterpret_cast<uint8_t *>(ws + small);
+    hipStream_t st = nullptr;
+    bn_status rs = BN_OK;
+    if (P.m > 0 &&
+        hipMemcpyAsync(dev_data, p->data, (size_t)P.n * P.m, hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+        rs = BN_EDEVICE;
+    if (rs == BN_OK) rs = enqueue_scores(P, p, dev_data, ws, st);
+    if (rs == BN_OK &&
+        hipMemcpyAsync(log_score, ws + P.o_logp, (size_t)P.n * P.K * 8, hipMemcpyDeviceToHost,
+                       st) != hipSuccess)
+        rs = BN_EDEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) rs = BN_EDEVICE;
+    (void)hipFree(ws);
+    return rs;
+}
+
+bn_status edge_posteriors_host(const bn_problem *p, bn_precision prec, double *post,
+                               bn_report *rep) {
+    bn_status s = validate(p, true, true);
+    if (s != BN_OK) return s;
+    if (!post) return BN_EINVAL;
+    if (prec != BN_FP64_LOG && prec != BN_FP32_SCALED) return BN_EINVAL;
+    Plan P = make_plan(p->n, p->d, p->m, prec, true, true);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return BN_EDEVICE;
+    if (P.total > free_b) return BN_ENOMEM;
+    char *ws = nullptr;
+    if (hipMalloc(&ws, P.total) != hipSuccess) return BN_ENOMEM;
+    hipStream_t st = nullptr;
+    PhaseEvents ev{};
+    bool timing = rep != nullptr;
+    if (timing)
+        for (int k = 0; k < 7; ++k) (void)hipEventCreate(&ev.ev[k]);
+    uint8_t *dev_data = reinterpret_cast<uint8_t *>(ws + P.o_data);
+    double *dev_post = reinterpret_cast<double *>(ws + P.o_post);
+    double *dev_diag = reinterpret_cast<double *>(ws + P.o_diag);
+    bn_status rs = BN_OK;
+    if (P.m > 0 &&
+        hipMemcpyAsync(dev_data, p->data, (size_t)P.n * P.m, hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+        rs = BN_EDEVICE;
+    if (rs == BN_OK)
+        rs = enqueue_solve(P, p, dev_data, ws, st, dev_post, dev_diag, timing ? &ev : nullptr);
+    double diag[16] = {0};
+    if (rs == BN_OK &&
+        hipMemcpyAsync(post, dev_post, (size_t)P.n * P.n * 8, hipMemcpyDeviceToHost, st) !=
+            hipSuccess)
+        rs = BN_EDEVICE;
+    if (rs == BN_OK &&
+        hipMemcpyAsync(diag, dev_diag, 8 * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+        rs = BN_EDEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) rs = BN_EDEVICE;
+    if (rs == BN_OK && rep) {
+        memset(rep, 0, sizeof(*rep));
+        rep->log_LV = diag[0];
+        rep->max_invariant_residual = diag[1];
+        rep->saturated = (uint64_t)diag[2];
+        rep->flushed = (uint64_t)diag[3];
+        float ms[7] = {0};
+        for (int k = 1; k < 7; ++k) (void)hipEventElapsedTime(&ms[k], ev.ev[k - 1], ev.ev[k]);
+        float tot = 0;
+        (void)hipEventElapsedTime(&tot, ev.ev[0], ev.ev[6]);
+        rep->ms_scores = ms[1];
+        rep->ms_alpha = ms[2];
+        rep->ms_fwd = ms[3];
+        rep->ms_bwd = ms[4];
+        rep->ms_gamma = ms[5];
+        rep->ms_edges = ms[6];
+        rep->ms_total = tot;
+    }
+    if (timing)
+        for (int k = 0; k < 7; ++k) (void)hipEventDestroy(ev.ev[k]);
+    (void)hipFree(ws);
+    return rs;
+}
+
+bn_status edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *dev_ws,
+                              size_t ws_bytes, void *hip_stream, double *dev_post,
+                              double *dev_diag) {
+    bn_status s = validate(p, false, false);
+    if (s != BN_OK) return s;
+    if (!dev_ws || !dev_post) return BN_EINVAL;
+    if (prec != BN_FP64_LOG && prec != BN_FP32_SCALED) return BN_EINVAL;
+    Plan P = make_plan(p->n, p->d, p->m, prec, false, false);
+    if (ws_bytes < P.total) return BN_EINVAL;
+    return enqueue_solve(P, p, p->data, reinterpret_cast<char *>(dev_ws),
+                         reinterpret_cast<hipStream_t>(hip_stream), dev_post, dev_diag, nullptr);
+}
+
+}  // namespace bnk
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+size_t bn_num_parent_sets(int32_t n, int32_t d) {
+    if (n < 1 || d < 0) return 0;
+    return (size_t)bnk::kcount_u64(n - 1, std::min(d, n - 1));
+}
+
+bn_status bn_local_scores(const bn_problem *p, double *log_score) {
+    return bnk::local_scores_host(p, log_score);
+}
+
+bn_status bn_workspace_bytes(int32_t n, int32_t d, int32_t m, bn_precision prec, size_t *bytes) {
+    if (!bytes || n < 2 || n > 31 || d < 0 || m < 0) return BN_EINVAL;
+    if (prec != BN_FP64_LOG && prec != BN_FP32_SCALED) return BN_EINVAL;
+    *bytes = bnk::make_plan(n, d, m, prec, false, false).total;
+    return BN_OK;
+}
+
+bn_status bn_edge_posteriors(const bn_problem *p, bn_precision prec, double *post,
+                             bn_report *rep) {
+    return bnk::edge_posteriors_host(p, prec, post, rep);
+}
+
+bn_status bn_edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *dev_ws,
+                                 size_t ws_bytes, void *hip_stream, double *dev_post,
+                                 double *dev_diag) {
+    return bnk::edge_posteriors_dev(p, prec, dev_ws, ws_bytes, hip_stream, dev_post, dev_diag);
+}
+
+const char *bn_status_string(bn_status s) {
+    switch (s) {
+        case BN_OK: return "ok";
+        case BN_EINVAL: return "invalid argument";
+        case BN_ENOMEM: return "out of device memory or budget";
+        case BN_EDEVICE: return "HIP runtime error";
+        case BN_EAGAIN: return "not ready";
+        case BN_ECANCELED: return "canceled";
+        case BN_EINTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

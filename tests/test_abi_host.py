@@ -1,0 +1,109 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every function declared in include/bn.h, and
+reject invalid problems before any device work.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1408_1664_amd as bn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built_library():
+    if not os.path.exists(bn.LIB_PATH):
+        from paper_1408_1664_amd import build
+        build.build()
+    return bn.lib()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "bn.h")).read()
+    return sorted(set(re.findall(r"\b(bn_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for want in ["bn_local_scores", "bn_edge_posteriors", "bn_edge_posteriors_dev",
+                 "bn_serve_submit", "bn_serve_poll", "bn_server_create", "bn_server_destroy",
+                 "bn_workspace_bytes", "bn_num_parent_sets", "bn_status_string"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", bn.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if " T " in l)
+    for name in _declared():
+        assert name in exported, name
+        assert hasattr(bn.lib(), name)
+
+
+def test_num_parent_sets():
+    from math import comb
+    for n in range(1, 32):
+        for d in range(0, 6):
+            want = sum(comb(n - 1, k) for k in range(min(d, n - 1) + 1))
+            assert bn.num_parent_sets(n, d) == want
+    assert bn.num_parent_sets(0, 2) == 0
+    assert bn.num_parent_sets(5, -1) == 0
+
+
+def test_workspace_grows_with_n_and_precision():
+    a = bn.workspace_bytes(20, 3, 500, "fp32")
+    b = bn.workspace_bytes(21, 3, 500, "fp32")
+    c = bn.workspace_bytes(20, 3, 500, "fp64")
+    assert b > 1.9 * a
+    assert c > a
+    # dominant terms: alpha n 2^(n-1) and the two 2^n sweeps
+    n = 25
+    w32 = bn.workspace_bytes(n, 4, 2000, "fp32")
+    assert w32 >= 5 * n * 2 ** (n - 1) + 2 * 5 * 2 ** n
+    w64 = bn.workspace_bytes(n, 4, 2000, "fp64")
+    assert w64 >= 8 * n * 2 ** (n - 1) + 2 * 8 * 2 ** n
+    with pytest.raises(bn.BnError):
+        bn.workspace_bytes(1, 2, 10, "fp32")
+    with pytest.raises(bn.BnError):
+        bn.workspace_bytes(32, 2, 10, "fp32")
+
+
+@pytest.mark.parametrize("case", ["n_small", "n_big", "arity1", "value_ge_arity", "ess0",
+                                  "neg_d", "bins"])
+def test_invalid_problems_rejected_before_device_work(case):
+    rng = np.random.default_rng(0)
+    data = rng.integers(0, 2, size=(6, 40)).astype(np.uint8)
+    arity = np.full(6, 2, np.uint8)
+    kw = dict(d=2, ess=1.0)
+    if case == "n_small":
+        data, arity = data[:1], arity[:1]
+    elif case == "n_big":
+        data = np.zeros((32, 4), np.uint8)
+        arity = np.full(32, 2, np.uint8)
+    elif case == "arity1":
+        arity = arity.copy(); arity[3] = 1
+    elif case == "value_ge_arity":
+        data = data.copy(); data[2, 7] = 2
+    elif case == "ess0":
+        kw["ess"] = 0.0
+    elif case == "neg_d":
+        kw["d"] = -1
+    elif case == "bins":
+        arity = np.full(6, 20, np.uint8)
+        data = (data * 19).astype(np.uint8)
+        kw["d"] = 3   # 20^4 bins > the histogram limit
+    for fn in (lambda: bn.local_scores(data, arity, kw["d"], ess=kw["ess"]),
+               lambda: bn.edge_posteriors(data, arity, kw["d"], "fp32", ess=kw["ess"])):
+        with pytest.raises(bn.BnError) as ei:
+            fn()
+        assert ei.value.status == bn.BN_EINVAL
+
+
+def test_status_strings():
+    assert bn.status_string(0) == "ok"
+    assert "invalid" in bn.status_string(-1)

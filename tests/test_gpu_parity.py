@@ -1,0 +1,164 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (absolute, on posteriors):
+* FP64 log-space form: 1e-10. Both sides evaluate the same sums in FP64
+  logarithms; they differ only in summation order (tree versus sequential),
+  i.e. by a few units of 2^-52 relative per value, far below 1e-10 even
+  after the ~n layers of the lattice.
+* FP32-scaled form: 1e-5, the target accuracy. FP32 rounding at each
+  operation is ~6e-8 relative; over the zeta passes and the lattice layers
+  the accumulated error stays around 1e-7..1e-6.
+Local scores: relative 1e-12 (both are sums of FP64 log-gamma values).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import paper_1408_1664_amd as bn
+from oracle import oracle as O
+from paper_1408_1664_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+def ranked_masks(N, d):
+    """Compressed parent-set masks in the library's rank order (size, then colex)."""
+    x = np.arange(1 << N, dtype=np.int64)
+    pc = np.zeros_like(x)
+    for b in range(N):
+        pc += (x >> b) & 1
+    return np.concatenate([x[pc == k] for k in range(min(d, N) + 1)])
+
+
+def expand(c, i):
+    low = c & ((1 << i) - 1)
+    return low | ((c >> i) << (i + 1))
+
+
+def _oracle(ds, d, ess=1.0, kind=O.BDEU, log_rho=None, log_q=None):
+    return O.edge_posteriors(ds.data, ds.arity, d, kind=kind, ess=ess, log_rho=log_rho,
+                             log_q=log_q)
+
+
+def _check(post, rep, ref, prec):
+    n = post.shape[0]
+    err = np.abs(post - ref["post"]).max()
+    print(f"  {prec}: max |dP| = {err:.3e}  log L(V) {rep['log_LV']:.6f} vs {ref['log_LV']:.6f}"
+          f"  resid {rep['max_invariant_residual']:.2e} sat {rep['saturated']} "
+          f"flush {rep['flushed']}", flush=True)
+    assert err <= TOL[prec]
+    assert np.all(np.diag(post) == 0)
+    assert abs(rep["log_LV"] - ref["log_LV"]) <= (1e-9 if prec == "fp64" else 1e-6) * max(
+        1.0, abs(ref["log_LV"]))
+    assert rep["max_invariant_residual"] < (1e-9 if prec == "fp64" else 1e-4)
+    assert rep["saturated"] == 0
+
+
+# ------------------------------------------------------------- a1 scores
+
+@pytest.mark.parametrize("name", ["n12_binary_m200_d3", "n20_ternary_m1000_d4"])
+def test_local_scores_match_oracle(name):
+    ds, p = datagen.workload(name)
+    n, d = ds.n, p["d"]
+    got = bn.local_scores(ds.data, ds.arity, d, ess=p["ess"])
+    ref = O.local_scores(ds.data, ds.arity, d, O.BDEU, p["ess"])
+    masks = ranked_masks(n - 1, d)
+    assert got.shape == (n, len(masks))
+    for i in range(n):
+        want = ref[i, expand(masks, i)]
+        np.testing.assert_allclose(got[i], want, rtol=1e-12, atol=1e-10)
+
+
+def test_local_scores_k2_mixed_arity():
+    ds = datagen.random_dag_dataset(9, 333, [2, 3, 4, 2, 5, 3, 2, 2, 3], 3, 0.7, seed=8)
+    got = bn.local_scores(ds.data, ds.arity, 3, score="k2")
+    ref = O.local_scores(ds.data, ds.arity, 3, O.K2)
+    masks = ranked_masks(8, 3)
+    for i in range(9):
+        np.testing.assert_allclose(got[i], ref[i, expand(masks, i)], rtol=1e-12, atol=1e-10)
+
+
+# ------------------------------------------------------- whole path, a1-a7
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["n12_binary_m200_d3", "n20_ternary_m1000_d4"])
+def test_posteriors_match_oracle(name, prec):
+    ds, p = datagen.workload(name)
+    ref = _oracle(ds, p["d"], p["ess"])
+    post, rep = bn.edge_posteriors(ds.data, ds.arity, p["d"], precision=prec, ess=p["ess"])
+    _check(post, rep, ref, prec)
+
+
+SMALL = [
+    # (n, m, arity, maxdeg, d, seed)
+    (2, 50, 2, 1, 1, 1), (3, 0, 2, 2, 2, 2), (4, 17, 3, 2, 1, 3), (5, 100, 2, 3, 0, 4),
+    (6, 250, [2, 3, 4, 2, 3, 2], 2, 2, 5), (7, 400, 2, 3, 6, 6), (9, 1000, 2, 3, 3, 7),
+    (11, 300, 3, 2, 2, 8), (13, 500, 2, 4, 4, 9), (14, 64, 2, 2, 3, 10),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", SMALL, ids=[f"n{c[0]}m{c[1]}d{c[4]}" for c in SMALL])
+def test_small_and_degenerate(case, prec):
+    n, m, ar, maxdeg, d, seed = case
+    ds = datagen.random_dag_dataset(n, m, ar, maxdeg, 1.0, seed=seed)
+    ref = _oracle(ds, d)
+    post, rep = bn.edge_posteriors(ds.data, ds.arity, d, precision=prec)
+    _check(post, rep, ref, prec)
+    if d == 0:
+        assert np.all(post == 0)
+
+
+TILES = ["1,1,1,1", "2,3,2,2", "3,4,3,3", "5,2,4,3", "4,6,2,5"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("tiles", TILES)
+def test_every_tiling_path(tiles, prec, monkeypatch):
+    """Small tiles force many sweep layers, multi-tile alpha and the two-level
+    Gamma reduction on problems the oracle solves instantly."""
+    monkeypatch.setenv("BN_TILE_BITS", tiles)
+    ds = datagen.random_dag_dataset(12, 300, 2, 3, 1.0, seed=77)
+    ref = _oracle(ds, 3)
+    post, rep = bn.edge_posteriors(ds.data, ds.arity, 3, precision=prec)
+    _check(post, rep, ref, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_custom_prior_and_k2(prec):
+    ds = datagen.random_dag_dataset(10, 400, 3, 3, 1.0, seed=12)
+    rng = np.random.default_rng(3)
+    log_rho = rng.normal(size=4)
+    log_q = rng.normal(size=10) * 3
+    ref = _oracle(ds, 3, kind=O.K2, log_rho=log_rho, log_q=log_q)
+    post, rep = bn.edge_posteriors(ds.data, ds.arity, 3, precision=prec, score="k2",
+                                   log_rho=log_rho, log_q=log_q)
+    _check(post, rep, ref, prec)
+
+
+def test_deterministic_bitwise():
+    ds, p = datagen.workload("n12_binary_m200_d3")
+    for prec in ("fp64", "fp32"):
+        a, _ = bn.edge_posteriors(ds.data, ds.arity, p["d"], precision=prec)
+        b, _ = bn.edge_posteriors(ds.data, ds.arity, p["d"], precision=prec)
+        assert np.array_equal(a, b)
+
+
+def test_device_entry_matches_host_entry():
+    import torch
+    ds, p = datagen.workload("n20_ternary_m1000_d4")
+    n, m = ds.n, ds.m
+    for prec in ("fp64", "fp32"):
+        host, rep = bn.edge_posteriors(ds.data, ds.arity, p["d"], precision=prec)
+        ws = torch.empty(bn.workspace_bytes(n, p["d"], m, prec), dtype=torch.uint8,
+                         device="cuda")
+        data = torch.from_numpy(ds.data).cuda()
+        post = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        diag = torch.zeros(8, dtype=torch.float64, device="cuda")
+        bn.edge_posteriors_dev(data, ds.arity, p["d"], prec, ws, post, diag)
+        torch.cuda.synchronize()
+        assert np.array_equal(post.cpu().numpy(), host)
+        assert diag[0].item() == pytest.approx(rep["log_LV"], abs=1e-12)
