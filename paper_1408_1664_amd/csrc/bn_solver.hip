@@ -147,10 +147,16 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.o_arity = take(64);
     P.o_rho = take(34 * 8);
     P.o_q = take(32 * 8);
-    P.o_logp = take((size_t)n * P.K * 8);
-    P.o_beta = take((size_t)n * P.K * V);
+    P.o_cnt = take(4 * 8);
+    P.o_diag = take(16 * 8);
+    P.o_resid = take(32 * 8);
+    P.o_layer = take(33 * V);
     P.o_qt = take(32 * V);
     P.o_gexp = take(64 * 8);
+    P.o_logp = take((size_t)n * P.K * 8);
+    // everything the local-score step touches lies below this offset
+    P.o_scores_end = o;
+    P.o_beta = take((size_t)n * P.K * V);
     if (P.x32) {
         P.o_alpha_f = take((size_t)n * NN * 4);
         P.o_alpha_b = take((size_t)n * NN);
@@ -168,10 +174,6 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
         P.o_Y2 = take((size_t)n * P.KG * P.KA * ((size_t)1 << (hG - P.aG)) * V);
     P.o_gam = take((size_t)n * P.K * V);
     P.o_part = take(((size_t)1 << nh) * (P.bL + 1) * V);
-    P.o_layer = take(33 * V);
-    P.o_resid = take(32 * 8);
-    P.o_diag = take(16 * 8);
-    P.o_cnt = take(4 * 8);
     if (with_post) P.o_post = take((size_t)n * n * 8);
     if (with_data) P.o_data = take((size_t)n * (size_t)std::max(m, 1));
     P.total = o;
@@ -292,11 +294,9 @@ bn_status local_scores_host(const bn_problem *p, double *log_score) {
     if (s != BN_OK) return s;
     if (!log_score) return BN_EINVAL;
     Plan P = make_plan(p->n, p->d, p->m, BN_FP64_LOG, true, false);
-    // only the tables, parameters, scores and data are needed
-    size_t need = std::max(P.o_logp + align256((size_t)P.n * P.K * 8), (size_t)0);
-    (void)need;
+    // the parameters, tables, counters and scores all lie below o_scores_end
     char *ws = nullptr;
-    size_t small = P.o_beta;  // everything before beta
+    const size_t small = P.o_scores_end;
     size_t data_bytes = (size_t)P.n * std::max(P.m, 1);
     if (hipMalloc(&ws, small + align256(data_bytes)) != hipSuccess) return BN_ENOMEM;
     uint8_t *dev_data = reinterpret_cast<uint8_t *>(ws + small);
