@@ -66,6 +66,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
                               "python paper_1408_1664_amd/build.py")
+        # torch ships its own copy of the HIP runtime under the same soname.
+        # Loading torch first makes the library bind to that copy, so one
+        # process never holds two HIP runtimes (which would hide the GPU from
+        # one of them).
+        try:
+            import torch  # noqa: F401
+        except Exception:  # torch absent: the library uses the system runtime
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P, I32, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64
         L.bn_num_parent_sets.argtypes = [I32, I32]
