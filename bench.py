@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Throughput of the exact edge-posterior path on one MI355X.
+
+One step = one whole solve (local scores, alpha, forward and backward
+sweeps, Gamma, edge sums and invariants) over one synthetic dataset that is
+already resident in HBM. Rate = n * 2^n lattice cells per second.
+
+Default headline: n = 30 binary variables, m = 500 samples, d = 3, FP32-scaled
+form. Comparison lines time the plain FP64 log-space form and n = 25. The CPU
+baseline is the oracle (FP64 log-space, OpenMP) on a bounded sample of the
+same dataset.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "n·2^n DP cells/s at n=25,30 (FP32-scaled vs FP64); served solves/s + p99"
+HBM_PEAK_GBS = 8000.0
+STORE_BYTES = {"fp32": 5, "fp64": 8}
+
+
+def phase_bytes(phase, n, prec):
+    """Algorithmic HBM bytes of one solve's phase: every value read or written
+    once (values: E bytes; alpha n 2^(n-1) entries, L and Rp 2^n each)."""
+    E = STORE_BYTES[prec]
+    A = n * 2 ** (n - 1)
+    if phase == "alpha":
+        return E * A                       # alpha written once
+    if phase in ("forward", "backward"):
+        return E * A + E * 2 ** n          # alpha read once, L (Rp) written once
+    if phase == "gamma":
+        return 2 * E * A                   # L(S) and Rp(S+v) read for every (S, v not in S)
+    return None
+
+
+def measure(bn, torch, datagen, name, prec, steps, warmup):
+    ds, p = datagen.workload(name)
+    n, m, d = ds.n, ds.m, p["d"]
+    ws = torch.empty(bn.workspace_bytes(n, d, m, prec), dtype=torch.uint8, device="cuda")
+    data = torch.from_numpy(ds.data).cuda()
+    post = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    diag = torch.zeros(8, dtype=torch.float64, device="cuda")
+    timers = [bn.Timer() for _ in range(warmup + steps)]
+
+    def solve(k):
+        bn.edge_posteriors_dev(data, ds.arity, d, prec, ws, post, diag, ess=p["ess"],
+                               timer=timers[k])
+
+    for k in range(warmup):
+        solve(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        solve(warmup + k)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    ph = [timers[warmup + k].read() for k in range(steps)]
+    phases = {key: sum(x[key] for x in ph) / steps for key in ph[0]}
+    dg = diag.cpu().tolist()
+    res = dict(workload=name, precision=prec, n=n, m=m, d=d, steps=steps, warmup=warmup,
+               seconds=sec, ms_per_step=1e3 * sec / steps,
+               cells_per_s=n * 2 ** n * steps / sec, phases_ms=phases, log_LV=dg[0],
+               max_invariant_residual=dg[1], saturated=int(dg[2]), flushed=int(dg[3]),
+               post=post.cpu().numpy())
+    for t in timers:
+        t.close()
+    del ws, data, post, diag
+    torch.cuda.empty_cache()
+    return res
+
+
+def roofline(res):
+    n, prec = res["n"], res["precision"]
+    ph = {k: v for k, v in res["phases_ms"].items() if k != "total"}
+    dom = max(ph, key=ph.get)
+    b = phase_bytes(dom, n, prec)
+    out = dict(kernel=dom, ms=ph[dom])
+    if b is None:
+        out.update(bound="alu", achieved=None, peak=None, unit=None, frac=None, traffic=None)
+        return out
+    ach = b / (ph[dom] * 1e-3) / 1e9
+    out.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+               frac=ach / HBM_PEAK_GBS, traffic=None, algorithmic_bytes=b)
+    return out
+
+
+def cpu_baseline(datagen, name, sample_n):
+    from oracle import oracle as O
+    ds, p = datagen.workload(name)
+    ns = min(sample_n, ds.n)
+    r = O.edge_posteriors(ds.data[:ns], ds.arity[:ns], p["d"], ess=p["ess"])
+    return dict(value=ns * 2 ** ns / r["seconds"], unit="cells/s", cores=O.num_threads(),
+                kind="oracle", seconds=r["seconds"],
+                sample=f"first {ns} of the {ds.n} variables of the {name} dataset "
+                       f"(same m={ds.m}, d={p['d']}): {ns}*2^{ns} cells, one solve")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="n30_binary_m500_d3")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--compare", default="fp64@n30_binary_m500_d3:3,"
+                                         "fp32@n25_binary_m2000_d4:10,"
+                                         "fp64@n25_binary_m2000_d4:5",
+                    help="extra lines prec@workload:steps, comma separated ('' for none)")
+    ap.add_argument("--cpu-sample-n", type=int, default=25)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the solve is single-GPU (multi-GPU sharding of "
+              "the lattice is a design, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1408_1664_amd as bn
+    from paper_1408_1664_amd import datagen
+
+    torch.cuda.set_device(0)
+    head = measure(bn, torch, datagen, args.workload, args.precision, args.steps, args.warmup)
+    print(f"# {args.workload} {args.precision}: {head['ms_per_step']:.2f} ms/step, "
+          f"{head['cells_per_s']:.3e} cells/s, phases {head['phases_ms']}", file=sys.stderr,
+          flush=True)
+    comps = []
+    for item in [c for c in args.compare.split(",") if c.strip()]:
+        pw, st = item.split(":")
+        prec, wl = pw.split("@")
+        r = measure(bn, torch, datagen, wl, prec, int(st), 1)
+        line = {k: v for k, v in r.items() if k != "post"}
+        if wl == args.workload and prec != args.precision:
+            line["max_abs_posterior_diff_vs_headline"] = float(np.abs(r["post"] -
+                                                                      head["post"]).max())
+        line["roofline"] = roofline(r)
+        comps.append(line)
+        print(f"# {wl} {prec}: {r['ms_per_step']:.2f} ms/step, {r['cells_per_s']:.3e} cells/s",
+              file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(datagen, args.workload, args.cpu_sample_n)
+    rf = roofline(head)
+    out = {
+        "metric": METRIC,
+        "value": head["cells_per_s"],
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": head["n"], "m": head["m"], "d": head["d"],
+                   "precision": "fp32_scaled" if args.precision == "fp32" else "fp64_log",
+                   "score": "BDeu(ess=1)", "prior": "q=1, rho_k=1/C(n-1,k)"},
+        "roofline": {k: rf[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_kernel": rf["kernel"],
+        "cpu_baseline": cpu,
+        "phases_ms": head["phases_ms"],
+        "log_LV": head["log_LV"],
+        "max_invariant_residual": head["max_invariant_residual"],
+        "saturated": head["saturated"],
+        "flushed": head["flushed"],
+        "comparisons": comps,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

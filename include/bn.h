@@ -107,8 +107,8 @@ size_t bn_num_parent_sets(int32_t n, int32_t d);
  *   are the set bit positions (sets by size, then in colex order).
  * Runs on the current HIP device and blocks until done.
  * BN_EINVAL: NULL pointers, n out of range, arity out of range, a data value
- * >= its arity, ess <= 0 (BDeu), d < 0, or a family with more than 2^20
- * parent-configuration x value bins.
+ * >= its arity, ess <= 0 (BDeu), d < 0, a family with more than 16384
+ * (parent configuration, child value) bins, or more than 2^31 - 1 families.
  */
 bn_status bn_local_scores(const bn_problem *p, double *log_score);
 
@@ -129,6 +129,8 @@ bn_status bn_workspace_bytes(int32_t n, int32_t d, int32_t m, bn_precision prec,
 bn_status bn_edge_posteriors(const bn_problem *p, bn_precision prec, double *post,
                              bn_report *rep);
 
+struct bn_timer;
+
 /*
  * Same computation with caller-supplied device memory and stream; nothing
  * is allocated. p->data must point to DEVICE memory (n*m bytes); arity,
@@ -137,7 +139,10 @@ bn_status bn_edge_posteriors(const bn_problem *p, bn_precision prec, double *pos
  *   hip_stream:      a hipStream_t (NULL: the default stream).
  *   dev_post:        DEVICE, n*n doubles, written as for bn_edge_posteriors.
  *   dev_diag:        DEVICE or NULL; 8 doubles: [0] log F(V), [1] max invariant
- *                    residual, [2] saturated count, [3] flushed count.
+ *                    residual, [2] saturated count, [3] flushed count,
+ *                    [4] |log Rp(empty) - log F(V)|, [5] max layer-sum residual,
+ *                    [6] max edge-sum residual.
+ *   timer:           NULL, or a bn_timer to receive per-phase HIP events.
  * Enqueues the work and returns without waiting; the results are valid after
  * the stream is synchronised. Data values are not range-checked on the host
  * (they live on the device); out-of-range values give undefined scores but
@@ -145,7 +150,26 @@ bn_status bn_edge_posteriors(const bn_problem *p, bn_precision prec, double *pos
  */
 bn_status bn_edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *dev_ws,
                                  size_t ws_bytes, void *hip_stream, double *dev_post,
-                                 double *dev_diag);
+                                 double *dev_diag, struct bn_timer *timer);
+
+/*
+ * Phase timer: HIP events that bn_edge_posteriors_dev records on the solve's
+ * own stream between its phases when a non-NULL timer is passed (recording
+ * does not synchronise). Create it on the device that runs the solves.
+ * bn_timer_read, valid once that stream has been synchronised, returns the
+ * milliseconds of the last solve that used the timer:
+ *   ms[0] parameters, tables, local scores and prior/gauges (a1)
+ *   ms[1] alpha, truncated upward zeta (a2)
+ *   ms[2] forward sweep, all layers (a3)
+ *   ms[3] backward sweep, all layers (a4)
+ *   ms[4] Gamma: product and truncated downward zeta (a5, a6)
+ *   ms[5] edge sums, invariants and diagnostics (a7)
+ *   ms[6] total
+ */
+typedef struct bn_timer bn_timer;
+bn_status bn_timer_create(bn_timer **timer);
+bn_status bn_timer_destroy(bn_timer *timer);
+bn_status bn_timer_read(const bn_timer *timer, double ms[7]);
 
 /*
  * Serving: a server thread batches solves of mixed n, m and arity as they

@@ -52,6 +52,16 @@ static double lae(double a, double b)
 
 static int popc(uint64_t x) { return __builtin_popcountll(x); }
 
+/* Threads an OpenMP region of the oracle will use. */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 static void set_threads(int nthreads)
 {
 #ifdef _OPENMP

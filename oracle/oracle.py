@@ -51,8 +51,15 @@ def _load():
                                            ctypes.c_int, ctypes.c_double, P, P, P, P,
                                            ctypes.c_int]
         lib.or_edge_posteriors.restype = ctypes.c_int
+        lib.or_num_threads.argtypes = []
+        lib.or_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle uses (OMP_NUM_THREADS or all cores)."""
+    return int(_load().or_num_threads())
 
 
 def _ptr(a):

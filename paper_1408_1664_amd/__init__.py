@@ -27,8 +27,9 @@ _PREC = {"fp64": FP64_LOG, "fp64_log": FP64_LOG, FP64_LOG: FP64_LOG,
 _SCORE = {"bdeu": SCORE_BDEU, "k2": SCORE_K2, SCORE_BDEU: SCORE_BDEU, SCORE_K2: SCORE_K2}
 
 EXPORTED = ["bn_num_parent_sets", "bn_local_scores", "bn_workspace_bytes",
-            "bn_edge_posteriors", "bn_edge_posteriors_dev", "bn_server_create",
-            "bn_serve_submit", "bn_serve_poll", "bn_server_destroy", "bn_status_string"]
+            "bn_edge_posteriors", "bn_edge_posteriors_dev", "bn_timer_create",
+            "bn_timer_destroy", "bn_timer_read", "bn_server_create", "bn_serve_submit",
+            "bn_serve_poll", "bn_server_destroy", "bn_status_string"]
 
 
 class BnError(RuntimeError):
@@ -84,7 +85,13 @@ def lib():
         L.bn_workspace_bytes.restype = ctypes.c_int
         L.bn_edge_posteriors.argtypes = [P, ctypes.c_int, P, P]
         L.bn_edge_posteriors.restype = ctypes.c_int
-        L.bn_edge_posteriors_dev.argtypes = [P, ctypes.c_int, P, ctypes.c_size_t, P, P, P]
+        L.bn_edge_posteriors_dev.argtypes = [P, ctypes.c_int, P, ctypes.c_size_t, P, P, P, P]
+        L.bn_timer_create.argtypes = [P]
+        L.bn_timer_create.restype = ctypes.c_int
+        L.bn_timer_destroy.argtypes = [P]
+        L.bn_timer_destroy.restype = ctypes.c_int
+        L.bn_timer_read.argtypes = [P, P]
+        L.bn_timer_read.restype = ctypes.c_int
         L.bn_edge_posteriors_dev.restype = ctypes.c_int
         L.bn_server_create.argtypes = [ctypes.c_size_t, I32, P]
         L.bn_server_create.restype = ctypes.c_int
@@ -169,8 +176,37 @@ def edge_posteriors(data, arity, d, precision="fp64", score="bdeu", ess=1.0, log
     return post, rep.as_dict()
 
 
+PHASES = ["scores", "alpha", "forward", "backward", "gamma", "edges", "total"]
+
+
+class Timer:
+    """Per-phase HIP events recorded by edge_posteriors_dev (bn_timer_*)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().bn_timer_create(ctypes.byref(h)), "bn_timer_create")
+        self._h = h
+
+    def read(self) -> dict:
+        ms = np.zeros(7, dtype=np.float64)
+        _check(lib().bn_timer_read(self._h, _ptr(ms)), "bn_timer_read")
+        return dict(zip(PHASES, ms.tolist()))
+
+    def close(self):
+        if self._h:
+            lib().bn_timer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def edge_posteriors_dev(data_dev, arity, d, precision, ws, post_dev, diag_dev=None,
-                        stream=None, score="bdeu", ess=1.0, log_rho=None, log_q=None):
+                        stream=None, score="bdeu", ess=1.0, log_rho=None, log_q=None,
+                        timer: "Timer | None" = None):
     """Enqueue a solve on device-resident inputs (torch tensors on the GPU).
 
     data_dev: uint8 [n, m] device tensor; ws: device tensor of at least
@@ -190,7 +226,8 @@ def edge_posteriors_dev(data_dev, arity, d, precision, ws, post_dev, diag_dev=No
                                         ws.numel() * ws.element_size(), ctypes.c_void_p(st),
                                         ctypes.c_void_p(post_dev.data_ptr()),
                                         None if diag_dev is None
-                                        else ctypes.c_void_p(diag_dev.data_ptr())),
+                                        else ctypes.c_void_p(diag_dev.data_ptr()),
+                                        None if timer is None else timer._h),
            "bn_edge_posteriors_dev")
 
 

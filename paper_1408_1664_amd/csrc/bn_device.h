@@ -46,6 +46,20 @@ struct PolLog {
                                         unsigned long long *) {
         s.p[i] = v;
     }
+    // four consecutive entries, i a multiple of 4
+    __device__ static inline void load4(const Store &s, uint64_t i, V *o) {
+        const double2 a = *reinterpret_cast<const double2 *>(s.p + i);
+        const double2 b = *reinterpret_cast<const double2 *>(s.p + i + 2);
+        o[0] = a.x;
+        o[1] = a.y;
+        o[2] = b.x;
+        o[3] = b.y;
+    }
+    __device__ static inline void store4(const Store &s, uint64_t i, const V *v,
+                                         unsigned long long *) {
+        *reinterpret_cast<double2 *>(s.p + i) = make_double2(v[0], v[1]);
+        *reinterpret_cast<double2 *>(s.p + i + 2) = make_double2(v[2], v[3]);
+    }
 };
 
 // ------------------------------------------------------- FP32 + exponent
@@ -124,6 +138,46 @@ struct PolX32 {
         }
         s.f[i] = v.f;
         s.b[i] = (uint8_t)b;
+    }
+    __device__ static inline void load4(const Store &s, uint64_t i, V *o) {
+        const float4 f = *reinterpret_cast<const float4 *>(s.f + i);
+        const uint32_t b = *reinterpret_cast<const uint32_t *>(s.b + i);
+        const float fs[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int bk = (b >> (8 * k)) & 0xff;
+            o[k] = bk ? X32{fs[k], bk - kX32Bias} : zero();
+        }
+    }
+    // Encode one value: returns the byte, writes the significand to *f.
+    __device__ static inline uint32_t encode(V v, float *f, unsigned long long *cnt) {
+        v = norm(v);
+        const int b = v.e + kX32Bias;
+        if (v.f == 0.0f) {
+            *f = 0.0f;
+            return 0;
+        }
+        if (b < 1) {
+            *f = 0.0f;
+            if (cnt) atomicAdd(cnt + 1, 1ull);
+            return 0;
+        }
+        if (b > 255) {
+            *f = 4.0e9f;
+            if (cnt) atomicAdd(cnt, 1ull);
+            return 255;
+        }
+        *f = v.f;
+        return (uint32_t)b;
+    }
+    __device__ static inline void store4(const Store &s, uint64_t i, const V *v,
+                                         unsigned long long *cnt) {
+        float f[4];
+        uint32_t b = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b |= encode(v[k], &f[k], cnt) << (8 * k);
+        *reinterpret_cast<float4 *>(s.f + i) = make_float4(f[0], f[1], f[2], f[3]);
+        *reinterpret_cast<uint32_t *>(s.b + i) = b;
     }
 };
 

@@ -91,6 +91,21 @@ __global__ void k_setup(Tables tb, int bL, int W, int bG, int d) {
     }
 }
 
+// Masks over w bits with at most d ones, ranked by size then colex order
+// (numeric order within a size). The w'-bit masks of size s, w' <= w, are the
+// first C(w', s) entries of the size-s section.
+__global__ void k_ranked(const uint32_t *binom, int w, int d, uint32_t *out) {
+    const uint32_t x = blockIdx.x * kThreads + threadIdx.x;
+    if (x >= (1u << w)) return;
+    const int k = __popc(x);
+    if (k > d) return;
+    uint32_t r = Kcount(binom, w, k - 1);
+    int j = 0;
+    for (int p = 0; p < w; ++p)
+        if ((x >> p) & 1) r += C(binom, p, ++j);
+    out[r] = x;
+}
+
 // Compressed parent-set masks in rank order, K(N,d) of them.
 __global__ void k_famask(const uint32_t *binom, int N, int d, uint32_t K, uint32_t *famask) {
     uint32_t r = blockIdx.x * kThreads + threadIdx.x;
@@ -217,103 +232,136 @@ __global__ void k_prep(int n, int d, uint32_t K, const uint32_t *binom,
 }
 
 // ------------------------------------------------ a2: alpha (upward zeta)
-// Workgroup (i, H): the tile of node i's lattice whose high N-bA bits are H.
-// Seeds Z(G_L) = sum_{G_H subset H, |G_H| <= d-|G_L|} beta_i(G_H + G_L) for
-// every |G_L| <= d, then the truncated upward zeta over the bA low bits
-// (bit j only touches masks with at most d ones above j: the others still
-// hold structural zeros), then alpha = q(|S|) * t(S).
-template <class P>
+__device__ inline double shfl_xor_v(double v, int m) { return __shfl_xor(v, m); }
+__device__ inline X32 shfl_xor_v(X32 v, int m) {
+    return X32{__shfl_xor(v.f, m), __shfl_xor(v.e, m)};
+}
+
+// Workgroup (i, H): the tile of node i's lattice (n-1 bits) whose high
+// N-bA bits are H; tile entry x = the low bA bits.
+//  1. Seeds Z(G_L) = sum_{G_H subset H, |G_H| <= d-|G_L|} beta_i(G_H + G_L) for
+//     every |G_L| <= d. The (seed, G_H) items are enumerated from a ranked
+//     table of small masks over the high bits; each seed is summed by a group
+//     of lanes of one wavefront and reduced by cross-lane shuffles.
+//  2. Truncated upward zeta over the low 8 bits in LDS: at bit j only masks
+//     with at most d ones above j can be nonzero (Def. 1; Alg. 2 predicate).
+//  3. The remaining RB = bA-8 bits in registers (entry x = reg * 256 + t),
+//     then alpha = q(|S|) * t(S), stored coalesced.
+template <class P, int RB>
 __global__ void __launch_bounds__(kThreads)
 k_alpha(int n, int d, uint32_t K, int bA, Tables tb, const typename P::V *__restrict__ beta,
         const typename P::V *__restrict__ qt, typename P::Store alpha,
         unsigned long long *cnt) {
     using V = typename P::V;
     extern __shared__ unsigned char smem[];
-    V *tile = reinterpret_cast<V *>(smem);
+    V *tile = reinterpret_cast<V *>(smem);                     // 2^bA
+    uint32_t *sbin = reinterpret_cast<uint32_t *>(tile + (1u << bA));  // 33 x 33
+    uint16_t *spat = reinterpret_cast<uint16_t *>(sbin + 33 * 33);    // K(bA-1, d)
     __shared__ int hb[32];
-    __shared__ int h_s;
-    __shared__ V red[kThreads];
+    __shared__ uint32_t offN[34];
+    __shared__ V sq[32];
     const int N = n - 1;
     const int hA = N - bA;
     const int i = blockIdx.x >> hA;
     const uint32_t H = blockIdx.x & ((1u << hA) - 1);
     const int t = threadIdx.x;
-    const uint32_t *bn = tb.binom;
-    if (t == 0) {
-        int h = 0;
-        for (int p = 0; p < hA; ++p)
-            if ((H >> p) & 1) hb[h++] = bA + p;
-        h_s = h;
-    }
+    for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
+    const uint32_t npat = Kcount(tb.binom, bA > 0 ? bA - 1 : 0, d);
+    for (uint32_t x = t; x < npat; x += kThreads) spat[x] = tb.pat[x];
+    if (t < hA && ((H >> t) & 1)) hb[__popc(H & ((1u << t) - 1))] = bA + t;
+    if (t < n) sq[t] = qt[t];
     for (uint32_t x = t; x < (1u << bA); x += kThreads) tile[x] = P::zero();
     __syncthreads();
-    const int h = h_s;
+    if (t <= d + 1) offN[t] = Kcount(sbin, N, t - 1);
+    __syncthreads();
+    const uint32_t *bn = sbin;
+    const int h = __popc(H);
     const V *bi = beta + (size_t)i * K;
-    // seeds, one size class s = |G_L| at a time
+
+    // 1. seeds, one size class s = |G_L| at a time
     for (int s = 0; s <= d && s <= bA; ++s) {
         const uint32_t nseed = C(bn, bA, s);
-        const int tt = d - s;                   // max |G_H|
+        const int tt = d - s;                       // max |G_H|
         const uint32_t items = Kcount(bn, h, tt);
-        int grp = 1;                             // threads per seed (power of 2, <= 64)
-        while (grp < 64 && (uint32_t)(grp * 2) * nseed <= kThreads) grp *= 2;
+        int grp = 1;                                // lanes per seed, power of 2 <= 64
+        while (grp < 64 && (uint32_t)grp < items && (uint32_t)(grp * 2) * nseed <= kThreads)
+            grp *= 2;
         const uint32_t per_round = kThreads / grp;
+        const uint32_t seedoff = Kcount(bn, bA, s - 1);
         for (uint32_t base = 0; base < nseed; base += per_round) {
             const uint32_t seed = base + t / grp;
             const int lane = t % grp;
             V acc = P::zero();
-            int gl[32];
             if (seed < nseed) {
-                colex_unrank(bn, seed, s, gl);
+                int k = 0;
+                uint32_t klo = 0, khi = 1;          // items of size k: [klo, khi)
+                uint32_t toff = 0;                  // item-table offset of size k
                 for (uint32_t it = lane; it < items; it += grp) {
-                    int k = 0;
-                    uint32_t off = 0;
-                    while (k < tt && it >= off + C(bn, h, k)) off += C(bn, h, k++);
-                    int e[32];
-                    colex_unrank(bn, it - off, k, e);
-                    uint32_t rank = Kcount(bn, N, s + k - 1) + seed;
-                    for (int q = 0; q < k; ++q) rank += C(bn, hb[e[q]], s + q + 1);
+                    while (it >= khi) {
+                        toff += C(bn, hA, k);
+                        ++k;
+                        klo = khi;
+                        khi += C(bn, h, k);
+                    }
+                    uint32_t m = tb.items[toff + (it - klo)];
+                    uint32_t rank = offN[s + k] + seed;
+                    int q = 0;
+                    while (m) {
+                        const int e = __ffs(m) - 1;
+                        m &= m - 1;
+                        rank += C(bn, hb[e], s + (++q));
+                    }
                     acc = P::add(acc, bi[rank]);
                 }
             }
-            // reduce over the grp lanes of each seed (fixed order)
-            red[t] = acc;
-            __syncthreads();
-            for (int w = grp / 2; w > 0; w >>= 1) {
-                if (lane < w) red[t] = P::add(red[t], red[t + w]);
-                __syncthreads();
-            }
-            if (lane == 0 && seed < nseed) {
-                uint32_t msk = 0;
-                for (int q = 0; q < s; ++q) msk |= 1u << gl[q];
-                tile[msk] = red[t];
-            }
-            __syncthreads();
+            for (int w = grp / 2; w > 0; w >>= 1) acc = P::add(acc, shfl_xor_v(acc, w));
+            if (lane == 0 && seed < nseed) tile[tb.seedA[seedoff + seed]] = acc;
         }
     }
-    // truncated upward zeta over the low bA bits
-    for (int j = 0; j < bA; ++j) {
-        const uint32_t np = Kcount(bn, bA - 1 - j, d);
-        const uint32_t cntj = np << j;
+    __syncthreads();
+
+    // 2. truncated upward zeta over the low min(bA, 8) bits in LDS
+    const int lb = bA < 8 ? bA : 8;
+    for (int j = 0; j < lb; ++j) {
+        const uint32_t cntj = Kcount(bn, bA - 1 - j, d) << j;
         for (uint32_t idx = t; idx < cntj; idx += kThreads) {
-            uint32_t lo = idx & ((1u << j) - 1);
-            uint32_t p = tb.pat[idx >> j];
-            uint32_t S = (p << (j + 1)) | (1u << j) | lo;
+            const uint32_t lo = idx & ((1u << j) - 1);
+            const uint32_t S = ((uint32_t)spat[idx >> j] << (j + 1)) | (1u << j) | lo;
             tile[S] = P::add(tile[S], tile[S ^ (1u << j)]);
         }
         __syncthreads();
     }
+
+    // 3. register bits and the store
     const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
-    for (uint32_t x = t; x < (1u << bA); x += kThreads) {
-        int k = h + __popc(x);
-        P::store(alpha, base + x, P::mul(qt[k], tile[x]), cnt);
+    if (RB == 0) {
+        for (uint32_t x = t; x < (1u << bA); x += kThreads)
+            P::store(alpha, base + x, P::mul(sq[h + __popc(x)], tile[x]), cnt);
+        return;
+    }
+    constexpr int R = 1 << RB;
+    V v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = tile[r * kThreads + t];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if ((r >> q) & 1) v[r] = P::add(v[r], v[r ^ (1 << q)]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t x = r * kThreads + t;
+        P::store(alpha, base + x, P::mul(sq[h + __popc(x)], v[r]), cnt);
     }
 }
 
 // ------------------------------------------- a3: forward sweep, one layer
 // Workgroup = tile H with |H| = h (H over the n-bL high bits). Cross-tile
-// terms (i in H) stream contiguous 2^bL blocks of alpha_i and L; in-tile
-// terms (i among the low bits) use the tile's alpha slices staged in LDS and
-// run popcount layer by popcount layer.
+// terms (i in H) stream contiguous 2^bL blocks of alpha_i and L, four
+// consecutive entries per thread, two nodes per iteration; in-tile terms (i
+// among the low bits) use the tile's alpha slices staged in LDS and run
+// popcount layer by popcount layer. Requires bL >= 2.
 template <class P>
 __global__ void __launch_bounds__(kThreads)
 k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Store L,
@@ -321,36 +369,64 @@ k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
     using V = typename P::V;
     extern __shared__ unsigned char smem[];
     const uint32_t half = 1u << (bL - 1);
+    const uint32_t T = 1u << bL;
     V *la = reinterpret_cast<V *>(smem);   // bL * half
     V *lt = la + (size_t)bL * half;        // 2^bL
+    uint16_t *lord = reinterpret_cast<uint16_t *>(lt + T);
+    __shared__ uint32_t loff[34];
+    __shared__ int pos[32];
     const int t = threadIdx.x;
-    const int nh = n - bL;
     const uint64_t NN = 1ull << (n - 1);
-    // H: the blockIdx.x-th h-subset of the high bits in colex order
-    int pos[32];
-    colex_unrank(tb.binom, blockIdx.x, h, pos);
+    if (t == 0) colex_unrank(tb.binom, blockIdx.x, h, pos);
+    if (t < bL + 2) loff[t] = tb.loff[t];
+    for (uint32_t x = t; x < T; x += kThreads) lord[x] = tb.lorder[x];
+    __syncthreads();
     uint64_t Hf = 0;
     for (int q = 0; q < h; ++q) Hf |= 1ull << (bL + pos[q]);
-    (void)nh;
-    const uint32_t T = 1u << bL;
-    for (uint32_t lo = t; lo < T; lo += kThreads) {
-        V acc = (Hf == 0 && lo == 0) ? P::one() : P::zero();
-        for (int q = 0; q < h; ++q) {
-            const int i = bL + pos[q];
-            const uint64_t Sm = (Hf ^ (1ull << i)) | lo;
-            acc = P::add(acc, P::mul(P::load(alpha, (uint64_t)i * NN + compress_bit(Sm, i)),
-                                     P::load(L, Sm)));
-        }
-        lt[lo] = acc;
-    }
+    // stage the in-tile alpha slices: alpha_i(Hf + Lo'), Lo' without i
     for (int i = 0; i < bL; ++i) {
         const uint64_t src = (uint64_t)i * NN + (Hf >> 1);
-        for (uint32_t k = t; k < half; k += kThreads) la[i * half + k] = P::load(alpha, src + k);
+        if (half >= 4) {
+            for (uint32_t k = 4 * t; k < half; k += 4 * kThreads)
+                P::load4(alpha, src + k, la + i * half + k);
+        } else {
+            for (uint32_t k = t; k < half; k += kThreads) la[i * half + k] = P::load(alpha, src + k);
+        }
+    }
+    // cross-tile terms
+    for (uint32_t lo = 4 * t; lo < T; lo += 4 * kThreads) {
+        V acc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = (Hf == 0 && lo + k == 0) ? P::one() : P::zero();
+        int q = 0;
+        for (; q + 1 < h; q += 2) {
+            const int i0 = bL + pos[q], i1 = bL + pos[q + 1];
+            const uint64_t S0 = (Hf ^ (1ull << i0)) | lo, S1 = (Hf ^ (1ull << i1)) | lo;
+            V a0[4], l0[4], a1[4], l1[4];
+            P::load4(alpha, (uint64_t)i0 * NN + compress_bit(S0, i0), a0);
+            P::load4(L, S0, l0);
+            P::load4(alpha, (uint64_t)i1 * NN + compress_bit(S1, i1), a1);
+            P::load4(L, S1, l1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                acc[k] = P::add(acc[k], P::add(P::mul(a0[k], l0[k]), P::mul(a1[k], l1[k])));
+        }
+        if (q < h) {
+            const int i0 = bL + pos[q];
+            const uint64_t S0 = (Hf ^ (1ull << i0)) | lo;
+            V a0[4], l0[4];
+            P::load4(alpha, (uint64_t)i0 * NN + compress_bit(S0, i0), a0);
+            P::load4(L, S0, l0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] = P::add(acc[k], P::mul(a0[k], l0[k]));
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lt[lo + k] = acc[k];
     }
     __syncthreads();
     for (int l = 1; l <= bL; ++l) {
-        for (uint32_t idx = tb.loff[l] + t; idx < tb.loff[l + 1]; idx += kThreads) {
-            const uint32_t lo = tb.lorder[idx];
+        for (uint32_t idx = loff[l] + t; idx < loff[l + 1]; idx += kThreads) {
+            const uint32_t lo = lord[idx];
             V acc = lt[lo];
             uint32_t rest = lo;
             while (rest) {
@@ -363,12 +439,12 @@ k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
         }
         __syncthreads();
     }
-    for (uint32_t lo = t; lo < T; lo += kThreads) P::store(L, Hf | lo, lt[lo], cnt);
+    for (uint32_t lo = 4 * t; lo < T; lo += 4 * kThreads) P::store4(L, Hf | lo, lt + lo, cnt);
 }
 
 // ----------------------------------------- a4: backward sweep, one layer
 // Rp(S) = sum_{i not in S} alpha_i(S) Rp(S + i), Rp(V) = 1; layers run from
-// the top. Same tiling as the forward sweep, mirrored.
+// the top. Same tiling as the forward sweep, mirrored. Requires bL >= 2.
 template <class P>
 __global__ void __launch_bounds__(kThreads)
 k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Store R,
@@ -376,35 +452,75 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
     using V = typename P::V;
     extern __shared__ unsigned char smem[];
     const uint32_t half = 1u << (bL - 1);
+    const uint32_t T = 1u << bL;
     V *la = reinterpret_cast<V *>(smem);
     V *lt = la + (size_t)bL * half;
+    uint16_t *lord = reinterpret_cast<uint16_t *>(lt + T);
+    __shared__ uint32_t loff[34];
+    __shared__ int pos[32];
+    __shared__ int outs[32];
+    __shared__ int nout_s;
     const int t = threadIdx.x;
     const int nh = n - bL;
     const uint64_t NN = 1ull << (n - 1);
-    int pos[32];
-    colex_unrank(tb.binom, blockIdx.x, h, pos);
+    if (t == 0) {
+        colex_unrank(tb.binom, blockIdx.x, h, pos);
+        uint32_t Hm = 0;
+        for (int q = 0; q < h; ++q) Hm |= 1u << pos[q];
+        int no = 0;
+        for (int p = 0; p < nh; ++p)
+            if (!((Hm >> p) & 1)) outs[no++] = bL + p;
+        nout_s = no;
+    }
+    if (t < bL + 2) loff[t] = tb.loff[t];
+    for (uint32_t x = t; x < T; x += kThreads) lord[x] = tb.lorder[x];
+    __syncthreads();
     uint64_t Hf = 0;
     for (int q = 0; q < h; ++q) Hf |= 1ull << (bL + pos[q]);
+    const int nout = nout_s;
     const uint64_t highall = ((1ull << nh) - 1) << bL;
-    const uint32_t T = 1u << bL;
-    for (uint32_t lo = t; lo < T; lo += kThreads) {
-        V acc = (Hf == highall && lo == T - 1) ? P::one() : P::zero();
-        const uint64_t Sm = Hf | lo;
-        for (int i = bL; i < n; ++i) {
-            if ((Hf >> i) & 1) continue;
-            acc = P::add(acc, P::mul(P::load(alpha, (uint64_t)i * NN + compress_bit(Sm, i)),
-                                     P::load(R, Sm | (1ull << i))));
-        }
-        lt[lo] = acc;
-    }
     for (int i = 0; i < bL; ++i) {
         const uint64_t src = (uint64_t)i * NN + (Hf >> 1);
-        for (uint32_t k = t; k < half; k += kThreads) la[i * half + k] = P::load(alpha, src + k);
+        if (half >= 4) {
+            for (uint32_t k = 4 * t; k < half; k += 4 * kThreads)
+                P::load4(alpha, src + k, la + i * half + k);
+        } else {
+            for (uint32_t k = t; k < half; k += kThreads) la[i * half + k] = P::load(alpha, src + k);
+        }
+    }
+    for (uint32_t lo = 4 * t; lo < T; lo += 4 * kThreads) {
+        V acc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            acc[k] = (Hf == highall && lo + k == T - 1) ? P::one() : P::zero();
+        const uint64_t Sm = Hf | lo;
+        int q = 0;
+        for (; q + 1 < nout; q += 2) {
+            const int i0 = outs[q], i1 = outs[q + 1];
+            V a0[4], r0[4], a1[4], r1[4];
+            P::load4(alpha, (uint64_t)i0 * NN + compress_bit(Sm, i0), a0);
+            P::load4(R, Sm | (1ull << i0), r0);
+            P::load4(alpha, (uint64_t)i1 * NN + compress_bit(Sm, i1), a1);
+            P::load4(R, Sm | (1ull << i1), r1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                acc[k] = P::add(acc[k], P::add(P::mul(a0[k], r0[k]), P::mul(a1[k], r1[k])));
+        }
+        if (q < nout) {
+            const int i0 = outs[q];
+            V a0[4], r0[4];
+            P::load4(alpha, (uint64_t)i0 * NN + compress_bit(Sm, i0), a0);
+            P::load4(R, Sm | (1ull << i0), r0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] = P::add(acc[k], P::mul(a0[k], r0[k]));
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lt[lo + k] = acc[k];
     }
     __syncthreads();
     for (int l = bL - 1; l >= 0; --l) {
-        for (uint32_t idx = tb.loff[l] + t; idx < tb.loff[l + 1]; idx += kThreads) {
-            const uint32_t lo = tb.lorder[idx];
+        for (uint32_t idx = loff[l] + t; idx < loff[l + 1]; idx += kThreads) {
+            const uint32_t lo = lord[idx];
             V acc = lt[lo];
             uint32_t rest = (T - 1) & ~lo;
             while (rest) {
@@ -417,7 +533,7 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
         }
         __syncthreads();
     }
-    for (uint32_t lo = t; lo < T; lo += kThreads) P::store(R, Hf | lo, lt[lo], cnt);
+    for (uint32_t lo = 4 * t; lo < T; lo += 4 * kThreads) P::store4(R, Hf | lo, lt + lo, cnt);
 }
 
 // ---------------------------------------- a5 + a6: Gamma, in-tile part
@@ -710,9 +826,16 @@ __global__ void k_finalize(int n, typename P::Store L, typename P::Store R,
         if (e_ != hipSuccess) return e_;                   \
     } while (0)
 
-hipError_t launch_setup(const Tables &tb, int bL, int W, int bG, int d, uint32_t N, uint32_t K,
-                        hipStream_t st) {
+hipError_t launch_setup(const Tables &tb, int bL, int W, int bG, int bA, int d, uint32_t N,
+                        uint32_t K, hipStream_t st) {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(kThreads), 0, st, tb, bL, W, bG, d);
+    BN_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_ranked, dim3(((1u << bA) + kThreads - 1) / kThreads), dim3(kThreads),
+                       0, st, (const uint32_t *)tb.binom, bA, d, tb.seedA);
+    BN_CHECK_LAUNCH();
+    const int hA = (int)N - bA;
+    hipLaunchKernelGGL(k_ranked, dim3(((1u << hA) + kThreads - 1) / kThreads), dim3(kThreads),
+                       0, st, (const uint32_t *)tb.binom, hA, d, tb.items);
     BN_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_famask, dim3((K + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
                        (const uint32_t *)tb.binom, (int)N, d, K, tb.famask);
@@ -754,14 +877,30 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     BN_CHECK_LAUNCH();
     rec(1);
     {
-        const size_t sm = sizeof(V) << a.bA;
-        hipLaunchKernelGGL(k_alpha<P>, dim3((unsigned)(n << (N - a.bA))), dim3(kThreads), sm, st,
-                           n, d, a.K, a.bA, tb, (const V *)beta, (const V *)qt, alpha, a.cnt);
+        const uint32_t npat = (uint32_t)a.npatA;
+        const size_t sm = (sizeof(V) << a.bA) + 33 * 33 * 4 + npat * 2;
+        const dim3 g((unsigned)(n << (N - a.bA)));
+        const int RB = a.bA > 8 ? a.bA - 8 : 0;
+#define BN_ALPHA(rb)                                                                           \
+    (void)hipFuncSetAttribute((const void *)k_alpha<P, rb>,                                    \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);            \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha<P, rb>), g, dim3(kThreads), sm, st, n, d, a.K, \
+                       a.bA, tb, (const V *)beta, (const V *)qt, alpha, a.cnt)
+        switch (RB) {
+            case 0: BN_ALPHA(0); break;
+            case 1: BN_ALPHA(1); break;
+            case 2: BN_ALPHA(2); break;
+            case 3: BN_ALPHA(3); break;
+            case 4: BN_ALPHA(4); break;
+            default: BN_ALPHA(5); break;
+        }
+#undef BN_ALPHA
         BN_CHECK_LAUNCH();
     }
     rec(2);
     const int nh = n - a.bL;
-    const size_t smL = sizeof(V) * (((size_t)a.bL << (a.bL - 1)) + ((size_t)1 << a.bL));
+    const size_t smL = sizeof(V) * (((size_t)a.bL << (a.bL - 1)) + ((size_t)1 << a.bL)) +
+                       2 * ((size_t)1 << a.bL);
     for (int h = 0; h <= nh; ++h) {
         const unsigned nb = a.tiles_per_layer[h];
         hipLaunchKernelGGL(k_fwd<P>, dim3(nb), dim3(kThreads), smL, st, n, a.bL, h, tb, alpha, L,

@@ -105,7 +105,7 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.x32 = (prec == BN_FP32_SCALED);
     const int N = P.N, d = P.d;
     P.K = (uint32_t)kcount_u64(N, d);
-    P.bA = std::min(N, 12);
+    P.bA = std::min(N, 13);
     P.bL = std::min(n, 10);
     P.bG = std::min(N, 12);
     P.aG = 12;
@@ -114,8 +114,8 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     if (const char *tb = getenv("BN_TILE_BITS")) {
         int v[4] = {P.bA, P.bL, P.bG, P.aG};
         if (sscanf(tb, "%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3]) == 4) {
-            P.bA = std::max(1, std::min(v[0], N));
-            P.bL = std::max(1, std::min(v[1], n));
+            P.bA = std::max(1, std::min(std::min(v[0], N), 13));
+            P.bL = std::max(2, std::min(v[1], n));
             P.bG = std::max(1, std::min(v[2], N));
             P.aG = std::max(1, std::min(v[3], 12));
         }
@@ -144,6 +144,8 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.o_pat = take(((size_t)1 << P.W) * 2);
     P.o_seed = take(P.KG * 4);
     P.o_famask = take((size_t)P.K * 4);
+    P.o_seedA = take(kcount_u64(P.bA, d) * 4);
+    P.o_items = take(kcount_u64(N - P.bA, d) * 4);
     P.o_arity = take(64);
     P.o_rho = take(34 * 8);
     P.o_q = take(32 * 8);
@@ -203,6 +205,8 @@ static Tables tables_of(const Plan &P, char *ws) {
     tb.pat = reinterpret_cast<uint16_t *>(ws + P.o_pat);
     tb.seedmask = reinterpret_cast<uint32_t *>(ws + P.o_seed);
     tb.famask = reinterpret_cast<uint32_t *>(ws + P.o_famask);
+    tb.seedA = reinterpret_cast<uint32_t *>(ws + P.o_seedA);
+    tb.items = reinterpret_cast<uint32_t *>(ws + P.o_items);
     return tb;
 }
 
@@ -230,7 +234,7 @@ static bn_status enqueue_scores(const Plan &P, const bn_problem *p, const uint8_
                        reinterpret_cast<double *>(ws + P.o_q), cnt);
     HIPCHK(hipGetLastError());
     Tables tb = tables_of(P, ws);
-    HIPCHK(launch_setup(tb, P.bL, P.W, P.bG, P.d, P.N, P.K, st));
+    HIPCHK(launch_setup(tb, P.bL, P.W, P.bG, P.bA, P.d, P.N, P.K, st));
     const int kind = p->score == BN_SCORE_K2 ? 1 : 0;
     HIPCHK(launch_scores(P.n, P.m, dev_data, reinterpret_cast<const uint8_t *>(ws + P.o_arity), P.K,
                          kind, p->ess, tb.famask, max_bins_of(p, P.d),
@@ -253,6 +257,7 @@ bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_d
     a.aG = P.aG;
     a.KG = P.KG;
     a.KA = P.KA;
+    a.npatA = (uint32_t)kcount_u64(std::max(P.bA - 1, 0), P.d);
     a.gauge = P.x32 ? 1 : 0;
     a.tb = tables_of(P, ws);
     a.logp = reinterpret_cast<const double *>(ws + P.o_logp);
@@ -378,7 +383,7 @@ bn_status edge_posteriors_host(const bn_problem *p, bn_precision prec, double *p
 
 bn_status edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *dev_ws,
                               size_t ws_bytes, void *hip_stream, double *dev_post,
-                              double *dev_diag) {
+                              double *dev_diag, PhaseEvents *ev) {
     bn_status s = validate(p, false, false);
     if (s != BN_OK) return s;
     if (!dev_ws || !dev_post) return BN_EINVAL;
@@ -386,7 +391,7 @@ bn_status edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *dev_
     Plan P = make_plan(p->n, p->d, p->m, prec, false, false);
     if (ws_bytes < P.total) return BN_EINVAL;
     return enqueue_solve(P, p, p->data, reinterpret_cast<char *>(dev_ws),
-                         reinterpret_cast<hipStream_t>(hip_stream), dev_post, dev_diag, nullptr);
+                         reinterpret_cast<hipStream_t>(hip_stream), dev_post, dev_diag, ev);
 }
 
 }  // namespace bnk
@@ -415,10 +420,52 @@ bn_status bn_edge_posteriors(const bn_problem *p, bn_precision prec, double *pos
     return bnk::edge_posteriors_host(p, prec, post, rep);
 }
 
+struct bn_timer {
+    bnk::PhaseEvents ev;
+};
+
 bn_status bn_edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *dev_ws,
                                  size_t ws_bytes, void *hip_stream, double *dev_post,
-                                 double *dev_diag) {
-    return bnk::edge_posteriors_dev(p, prec, dev_ws, ws_bytes, hip_stream, dev_post, dev_diag);
+                                 double *dev_diag, bn_timer *timer) {
+    return bnk::edge_posteriors_dev(p, prec, dev_ws, ws_bytes, hip_stream, dev_post, dev_diag,
+                                    timer ? &timer->ev : nullptr);
+}
+
+bn_status bn_timer_create(bn_timer **timer) {
+    if (!timer) return BN_EINVAL;
+    bn_timer *t = new bn_timer();
+    for (int k = 0; k < 7; ++k) {
+        if (hipEventCreate(&t->ev.ev[k]) != hipSuccess) {
+            for (int j = 0; j < k; ++j) (void)hipEventDestroy(t->ev.ev[j]);
+            delete t;
+            return BN_EDEVICE;
+        }
+    }
+    t->ev.ev[7] = nullptr;
+    *timer = t;
+    return BN_OK;
+}
+
+bn_status bn_timer_destroy(bn_timer *timer) {
+    if (!timer) return BN_EINVAL;
+    for (int k = 0; k < 7; ++k) (void)hipEventDestroy(timer->ev.ev[k]);
+    delete timer;
+    return BN_OK;
+}
+
+bn_status bn_timer_read(const bn_timer *timer, double ms[7]) {
+    if (!timer || !ms) return BN_EINVAL;
+    for (int k = 1; k < 7; ++k) {
+        float x = 0;
+        if (hipEventElapsedTime(&x, timer->ev.ev[k - 1], timer->ev.ev[k]) != hipSuccess)
+            return BN_EDEVICE;
+        ms[k - 1] = x;
+    }
+    float tot = 0;
+    if (hipEventElapsedTime(&tot, timer->ev.ev[0], timer->ev.ev[6]) != hipSuccess)
+        return BN_EDEVICE;
+    ms[6] = tot;
+    return BN_OK;
 }
 
 const char *bn_status_string(bn_status s) {
