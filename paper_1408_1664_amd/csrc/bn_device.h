@@ -20,7 +20,7 @@
 namespace bnk {
 
 constexpr int kX32Bias = 200;
-constexpr int kEZero = -(1 << 20);   // exponent carried by an exact zero
+constexpr int kEZero = -(1 << 26);   // exponent carried by an exact zero
 
 // ---------------------------------------------------------------- FP64 log
 struct PolLog {
@@ -63,9 +63,11 @@ struct PolLog {
 };
 
 // ------------------------------------------------------- FP32 + exponent
+// In registers and LDS the exponent is kept in binary orders (a multiple of
+// 64): value = f * 2^E. HBM holds the byte b = E/64 + kX32Bias.
 struct X32 {
     float f;
-    int e;
+    int e;  // E, a multiple of 64
 };
 
 struct PolX32 {
@@ -80,79 +82,44 @@ struct PolX32 {
     // Bring f back into [2^-32, 2^32) (f >= 0, normal or zero).
     __device__ static inline V norm(V x) {
         if (!(x.f > 0.0f)) return zero();
-        int bits = __float_as_int(x.f);
-        int k = ((bits >> 23) & 0xff) - 127;
-        int s = (k + 32) >> 6;  // floor((k + 32) / 64)
+        const int bits = __float_as_int(x.f);
+        const int k = ((bits >> 23) & 0xff) - 127;
+        const int s = (k + 32) >> 6;  // floor((k + 32) / 64)
         x.f = __int_as_float(bits - (s << 29));
-        x.e += s;
+        x.e += s << 6;
         return x;
     }
     __device__ static inline V mul(V a, V b) { return norm(X32{a.f * b.f, a.e + b.e}); }
     // Exact alignment to the larger exponent; the smaller operand is scaled
-    // by 2^(-64 * delta) (it underflows to zero only when it is below FP32
-    // resolution of the result).
+    // by an exact power of two (it underflows to zero only when it is below
+    // FP32 resolution of the result).
     __device__ static inline V add(V a, V b) {
-        int em = max(a.e, b.e);
-        float fa = ldexpf(a.f, (a.e - em) * 64);
-        float fb = ldexpf(b.f, (b.e - em) * 64);
-        return X32{fa + fb, em};
+        const int em = max(a.e, b.e);
+        return X32{ldexpf(a.f, a.e - em) + ldexpf(b.f, b.e - em), em};
     }
     __device__ static inline V from_log(double x) {
         if (!(x > -1e300)) return zero();
-        double t = x * 1.4426950408889634074;  // log2
-        int e = (int)floor((t + 32.0) / 64.0);
-        float f = (float)exp(x - (double)e * 64.0 * 0.69314718055994530942);
-        return norm(X32{f, e});
+        const double t = x * 1.4426950408889634074;  // log2
+        const int e = (int)floor((t + 32.0) / 64.0);
+        const float f = (float)exp(x - (double)e * 64.0 * 0.69314718055994530942);
+        return norm(X32{f, e * 64});
     }
     __device__ static inline double to_log(V v) {
         if (!(v.f > 0.0f)) return -__builtin_huge_val();
-        return log((double)v.f) + (double)v.e * 64.0 * 0.69314718055994530942;
+        return log((double)v.f) + (double)v.e * 0.69314718055994530942;
     }
     __device__ static inline double log_ratio(V a, V b) { return to_log(a) - to_log(b); }
+    __device__ static inline V decode(float f, int b) {
+        return b ? X32{f, (b - kX32Bias) << 6} : zero();
+    }
     __device__ static inline V load(const Store &s, uint64_t i) {
-        uint8_t b = s.b[i];
-        if (b == 0) return zero();
-        return X32{s.f[i], (int)b - kX32Bias};
-    }
-    // cnt[0] counts saturations, cnt[1] flushes of nonzero values.
-    __device__ static inline void store(const Store &s, uint64_t i, V v,
-                                        unsigned long long *cnt) {
-        v = norm(v);
-        int b = v.e + kX32Bias;
-        if (v.f == 0.0f) {
-            s.f[i] = 0.0f;
-            s.b[i] = 0;
-            return;
-        }
-        if (b < 1) {
-            s.f[i] = 0.0f;
-            s.b[i] = 0;
-            if (cnt) atomicAdd(cnt + 1, 1ull);
-            return;
-        }
-        if (b > 255) {
-            s.f[i] = 4.0e9f;
-            s.b[i] = 255;
-            if (cnt) atomicAdd(cnt, 1ull);
-            return;
-        }
-        s.f[i] = v.f;
-        s.b[i] = (uint8_t)b;
-    }
-    __device__ static inline void load4(const Store &s, uint64_t i, V *o) {
-        const float4 f = *reinterpret_cast<const float4 *>(s.f + i);
-        const uint32_t b = *reinterpret_cast<const uint32_t *>(s.b + i);
-        const float fs[4] = {f.x, f.y, f.z, f.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int bk = (b >> (8 * k)) & 0xff;
-            o[k] = bk ? X32{fs[k], bk - kX32Bias} : zero();
-        }
+        return decode(s.f[i], s.b[i]);
     }
     // Encode one value: returns the byte, writes the significand to *f.
+    // cnt[0] counts saturations, cnt[1] flushes of nonzero values.
     __device__ static inline uint32_t encode(V v, float *f, unsigned long long *cnt) {
         v = norm(v);
-        const int b = v.e + kX32Bias;
+        const int b = (v.e >> 6) + kX32Bias;
         if (v.f == 0.0f) {
             *f = 0.0f;
             return 0;
@@ -169,6 +136,21 @@ struct PolX32 {
         }
         *f = v.f;
         return (uint32_t)b;
+    }
+    __device__ static inline void store(const Store &s, uint64_t i, V v,
+                                        unsigned long long *cnt) {
+        float f;
+        const uint32_t b = encode(v, &f, cnt);
+        s.f[i] = f;
+        s.b[i] = (uint8_t)b;
+    }
+    __device__ static inline void load4(const Store &s, uint64_t i, V *o) {
+        const float4 f = *reinterpret_cast<const float4 *>(s.f + i);
+        const uint32_t b = *reinterpret_cast<const uint32_t *>(s.b + i);
+        o[0] = decode(f.x, b & 0xff);
+        o[1] = decode(f.y, (b >> 8) & 0xff);
+        o[2] = decode(f.z, (b >> 16) & 0xff);
+        o[3] = decode(f.w, b >> 24);
     }
     __device__ static inline void store4(const Store &s, uint64_t i, const V *v,
                                          unsigned long long *cnt) {

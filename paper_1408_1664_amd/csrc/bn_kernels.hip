@@ -537,46 +537,143 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
 }
 
 // ---------------------------------------- a5 + a6: Gamma, in-tile part
-// Workgroup (v, Hc): tile of v's compressed lattice with high bits Hc.
-// g_v(S) = q(|S|) L(S) Rp(S + v) is formed on the fly, then the truncated
-// downward zeta over the bG low bits (bit j only updates masks with at most
-// d ones among the bits below j: the rest can never reach an output), and
-// the K(bG,d) entries with |G_L| <= d are written to Y1[v][seed][Hc].
-template <class P>
+// Workgroup = full-mask tile H (the low bT bits vary). L(H + x) stays in
+// registers and Rp(H + x) in LDS for the whole workgroup; every endpoint v
+// not in H is served in turn:
+//   g_v(S) = q(|S|) L(S) Rp(S + v), S = H + x, x without bit v when v is a
+//   tile bit (Rp(S + v) then sits in the same tile); for v above the tile
+//   Rp(S + v) is the tile H + v, prefetched while the previous v is reduced;
+//   truncated downward zeta over the tile bits other than v: the register
+//   bits (entry x = reg * 256 + t) densely, then the low 8 bits in LDS,
+//   where bit j only updates masks with at most d ones among the bits
+//   already processed (Def. 2; Alg. 3 predicate);
+//   the entries with at most d ones go to Y1_v[seed][Hc_v].
+// Tiles are mapped so that consecutive H run on the same XCD, which lets
+// the L2 merge the 8-byte Y1 writes of neighbouring tiles.
+template <class P, int RB>
 __global__ void __launch_bounds__(kThreads)
-k_gamma_tile(int n, int d, int bG, uint32_t KG, Tables tb, typename P::Store L,
+k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
              typename P::Store R, const typename P::V *__restrict__ qt,
              typename P::V *__restrict__ Y1) {
     using V = typename P::V;
+    constexpr int NR = 1 << RB;
     extern __shared__ unsigned char smem[];
-    V *tile = reinterpret_cast<V *>(smem);
-    const int N = n - 1;
-    const int hG = N - bG;
-    const int v = blockIdx.x >> hG;
-    const uint32_t Hc = blockIdx.x & ((1u << hG) - 1);
+    const uint32_t T = 1u << bT;
+    V *Rt = reinterpret_cast<V *>(smem);
+    V *gb = Rt + T;
+    uint32_t *sbin = reinterpret_cast<uint32_t *>(gb + T);
+    uint32_t *seedT = sbin + 33 * 33;
+    uint16_t *spat = reinterpret_cast<uint16_t *>(seedT + gg.KT);
+    __shared__ V sq[32];
     const int t = threadIdx.x;
-    const uint32_t *bn = tb.binom;
-    const uint64_t bv = 1ull << v;
-    for (uint32_t x = t; x < (1u << bG); x += kThreads) {
-        const uint64_t c = ((uint64_t)Hc << bG) | x;
-        const uint64_t S = expand_bit(c, v);
-        tile[x] = P::mul(qt[__popcll(S)], P::mul(P::load(L, S), P::load(R, S | bv)));
+    const int lb = bT < 8 ? bT : 8;          // thread bits of the tile
+    const int hbits = n - bT;
+    const uint32_t nblk = 1u << hbits;
+    uint32_t H = blockIdx.x;
+    if (nblk >= 64) H = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
+    const uint64_t Hf = (uint64_t)H << bT;
+    for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
+    for (uint32_t x = t; x < gg.KT; x += kThreads) seedT[x] = tb.seedmask[x];
+    for (uint32_t x = t; x < gg.npat; x += kThreads) spat[x] = tb.pat[x];
+    if (t < n) sq[t] = qt[t];
+    V Lr[NR], Rv[NR], g[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const uint32_t x = r * kThreads + t;
+        if (x < T) {
+            Lr[r] = P::load(L, Hf | x);
+            Rt[x] = P::load(R, Hf | x);
+        }
+    }
+    int vn = bT;                              // next endpoint above the tile, not in H
+    while (vn < n && ((Hf >> vn) & 1)) ++vn;
+    if (vn < n) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const uint32_t x = r * kThreads + t;
+            if (x < T) Rv[r] = P::load(R, Hf | x | (1ull << vn));
+        }
     }
     __syncthreads();
-    for (int j = 0; j < bG; ++j) {
-        const uint32_t np = Kcount(bn, j, d);
-        const uint32_t cntj = np << (bG - 1 - j);
-        for (uint32_t idx = t; idx < cntj; idx += kThreads) {
-            const uint32_t hi = idx / np;
-            const uint32_t p = tb.pat[idx - hi * np];
-            const uint32_t Tm = (hi << (j + 1)) | p;
-            tile[Tm] = P::add(tile[Tm], tile[Tm | (1u << j)]);
+    const uint32_t *bn = sbin;
+    for (int v = 0; v < n; ++v) {
+        const bool low = v < bT;
+        if (!low && ((Hf >> v) & 1)) continue;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const uint32_t x = r * kThreads + t;
+            if (x >= T) continue;
+            if (low && ((x >> v) & 1)) {
+                g[r] = P::zero();
+                continue;
+            }
+            const V q = sq[__popcll(Hf | x)];   // |S| <= n-1 since v is not in S
+            g[r] = P::mul(q, P::mul(Lr[r], low ? Rt[x | (1u << v)] : Rv[r]));
+        }
+        if (!low) {                           // prefetch the next endpoint's Rp tile
+            vn = v + 1;
+            while (vn < n && ((Hf >> vn) & 1)) ++vn;
+            if (vn < n) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const uint32_t x = r * kThreads + t;
+                    if (x < T) Rv[r] = P::load(R, Hf | x | (1ull << vn));
+                }
+            }
+        }
+        // register bits (downward, dense), skipping bit v
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            if (low && v == lb + q) continue;
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (!((r >> q) & 1)) g[r] = P::add(g[r], g[r | (1 << q)]);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const uint32_t x = r * kThreads + t;
+            if (x < T) gb[x] = g[r];
+        }
+        __syncthreads();
+        // thread bits in LDS, truncated on the bits already processed
+        for (int j = 0; j < lb; ++j) {
+            if (j == v) continue;
+            const uint32_t np = Kcount(bn, j + RB, d);
+            const uint32_t nfree = 1u << (lb - 1 - j);
+            const uint32_t cnt = np * nfree;
+            for (uint32_t idx = t; idx < cnt; idx += kThreads) {
+                const uint32_t pi = idx / nfree;
+                const uint32_t f = idx - pi * nfree;
+                const uint32_t p = spat[pi];
+                const uint32_t Tm = (p & ((1u << j) - 1)) | ((p >> j) << lb) | (f << (j + 1));
+                gb[Tm] = P::add(gb[Tm], gb[Tm | (1u << j)]);
+            }
+            __syncthreads();
+        }
+        // outputs: masks with at most d ones (and without bit v)
+        const int hv = gg.hv[v];
+        const uint32_t Hc = low ? H : (uint32_t)compress_bit(H, v - bT);
+        V *dst = Y1 + gg.y1off[v];
+        for (uint32_t si = t; si < gg.KT; si += kThreads) {
+            const uint32_t msk = seedT[si];
+            uint32_t rank = si;
+            if (low) {
+                if ((msk >> v) & 1) continue;
+                const uint32_t cm = (uint32_t)compress_bit(msk, v);
+                const int sg = __popc(cm);
+                rank = Kcount(bn, bT - 1, sg - 1);
+                int k = 0;
+                uint32_t rest = cm;
+                while (rest) {
+                    const int p = __ffs(rest) - 1;
+                    rest &= rest - 1;
+                    rank += C(bn, p, ++k);
+                }
+            }
+            dst[((size_t)rank << hv) + Hc] = gb[msk];
         }
         __syncthreads();
     }
-    const size_t stride = (size_t)1 << hG;
-    for (uint32_t s = t; s < KG; s += kThreads)
-        Y1[((size_t)v * KG + s) * stride + Hc] = tile[tb.seedmask[s]];
 }
 
 // Output rank (within node v's ranked parent sets) of G_L + (high pattern
@@ -593,33 +690,49 @@ __device__ inline uint32_t out_rank(const uint32_t *bn, int N, int sigma, uint32
     return Kcount(bn, N, sigma + k - 1) + r;
 }
 
+// Seed of endpoint v's compressed tile: size class and colex rank of the
+// s-th ranked mask over bv bits.
+__device__ inline void seed_of(const uint32_t *bn, int bv, uint32_t s, int *sigma, uint32_t *cl) {
+    int k = 0;
+    uint32_t off = 0;
+    while (s >= off + C(bn, bv, k)) off += C(bn, bv, k++);
+    *sigma = k;
+    *cl = s - off;
+}
+
+// Locate (v, local index) of a flat block index over per-v block counts.
+__device__ inline int find_v(const uint32_t *pref, int n, uint32_t b) {
+    int v = 0;
+    while (v + 1 < n + 1 && pref[v + 1] <= b) ++v;
+    return v;
+}
+
 // ---------------------------------- a6: Gamma, high bits, one level
-// Workgroup (v, seed): the vector Y1[v][seed][.] over the hG high bits;
+// Workgroup (v, seed): the vector Y1_v[seed][.] over v's hv high bits;
 // truncated downward zeta keeping |G_H| <= d - |G_L|; writes Gamma_v.
 template <class P>
 __global__ void __launch_bounds__(kThreads)
-k_gamma_high1(int n, int d, int bG, uint32_t KG, uint32_t K, Tables tb,
+k_gamma_high1(int n, int d, uint32_t K, GammaGeom gg, Tables tb,
               const typename P::V *__restrict__ Y1, typename P::V *__restrict__ gam) {
     using V = typename P::V;
     extern __shared__ unsigned char smem[];
     V *vec = reinterpret_cast<V *>(smem);
     const int N = n - 1;
-    const int hG = N - bG;
-    const int v = blockIdx.x / KG;
-    const uint32_t s = blockIdx.x % KG;
+    const int v = find_v(gg.blk1, n, blockIdx.x);
+    const uint32_t s = blockIdx.x - gg.blk1[v];
     const int t = threadIdx.x;
     const uint32_t *bn = tb.binom;
-    const uint32_t gl = tb.seedmask[s];
-    const int sigma = __popc(gl);
+    const int bv = gg.bv[v], hv = gg.hv[v];
+    int sigma;
+    uint32_t cl;
+    seed_of(bn, bv, s, &sigma, &cl);
     const int tr = d - sigma;
-    const uint32_t cl = s - Kcount(bn, bG, sigma - 1);
-    const size_t stride = (size_t)1 << hG;
-    const V *src = Y1 + ((size_t)v * KG + s) * stride;
-    for (uint32_t x = t; x < (1u << hG); x += kThreads) vec[x] = src[x];
+    const V *src = Y1 + gg.y1off[v] + ((size_t)s << hv);
+    for (uint32_t x = t; x < (1u << hv); x += kThreads) vec[x] = src[x];
     __syncthreads();
-    for (int j = 0; j < hG; ++j) {
+    for (int j = 0; j < hv; ++j) {
         const uint32_t cntj = Kcount(bn, j, d);  // walk the d-table, skip > tr
-        const uint32_t tot = cntj << (hG - 1 - j);
+        const uint32_t tot = cntj << (hv - 1 - j);
         for (uint32_t idx = t; idx < tot; idx += kThreads) {
             const uint32_t hi = idx / cntj;
             const uint32_t p = tb.pat[idx - hi * cntj];
@@ -629,34 +742,37 @@ k_gamma_high1(int n, int d, int bG, uint32_t KG, uint32_t K, Tables tb,
         }
         __syncthreads();
     }
-    const uint32_t npat = Kcount(bn, hG, d);
+    const uint32_t npat = Kcount(bn, hv, d);
     for (uint32_t idx = t; idx < npat; idx += kThreads) {
         const uint32_t x = tb.pat[idx];
         if (__popc(x) > tr) continue;
-        gam[(size_t)v * K + out_rank(bn, N, sigma, cl, x, bG)] = vec[x];
+        gam[(size_t)v * K + out_rank(bn, N, sigma, cl, x, bv)] = vec[x];
     }
 }
 
 // ------------------------------- a6: Gamma, high bits, two levels (A, B)
 // Level A, workgroup (v, seed, Ht): the low a bits of Hc; output for every
-// a-bit pattern p with at most d ones: Y2[v][seed][p][Ht].
+// a-bit pattern p with at most d ones: Y2_v[seed][p][Ht].
 template <class P>
 __global__ void __launch_bounds__(kThreads)
-k_gamma_highA(int n, int d, int bG, int a, uint32_t KG, uint32_t KA, Tables tb,
+k_gamma_highA(int n, int d, int a, uint32_t KA, GammaGeom gg, Tables tb,
               const typename P::V *__restrict__ Y1, typename P::V *__restrict__ Y2) {
     using V = typename P::V;
     extern __shared__ unsigned char smem[];
     V *vec = reinterpret_cast<V *>(smem);
-    const int N = n - 1;
-    const int hG = N - bG;
-    const int hB = hG - a;
-    const uint32_t Ht = blockIdx.x & ((1u << hB) - 1);
-    const uint32_t vs = blockIdx.x >> hB;     // v * KG + seed
-    const uint32_t s = vs % KG;
+    const int v = find_v(gg.blkA, n, blockIdx.x);
+    const uint32_t local = blockIdx.x - gg.blkA[v];
+    const int bv = gg.bv[v], hv = gg.hv[v];
+    const int hB = hv - a;
+    const uint32_t Ht = local & ((1u << hB) - 1);
+    const uint32_t s = local >> hB;
     const int t = threadIdx.x;
     const uint32_t *bn = tb.binom;
-    const int tr = d - __popc(tb.seedmask[s]);
-    const V *src = Y1 + ((size_t)vs << hG) + ((size_t)Ht << a);
+    int sigma;
+    uint32_t cl;
+    seed_of(bn, bv, s, &sigma, &cl);
+    const int tr = d - sigma;
+    const V *src = Y1 + gg.y1off[v] + ((size_t)s << hv) + ((size_t)Ht << a);
     for (uint32_t x = t; x < (1u << a); x += kThreads) vec[x] = src[x];
     __syncthreads();
     for (int j = 0; j < a; ++j) {
@@ -671,49 +787,46 @@ k_gamma_highA(int n, int d, int bG, int a, uint32_t KG, uint32_t KA, Tables tb,
         }
         __syncthreads();
     }
-    for (uint32_t pi = t; pi < KA; pi += kThreads) {
-        const uint32_t x = tb.pat[pi];
-        Y2[(((size_t)vs * KA + pi) << hB) + Ht] = vec[x];
-    }
+    V *dst = Y2 + gg.y2off[v];
+    for (uint32_t pi = t; pi < KA; pi += kThreads)
+        dst[(((size_t)s * KA + pi) << hB) + Ht] = vec[tb.pat[pi]];
 }
 
 // Level B, workgroup (v, seed): for each a-bit pattern p and each output
 // pattern y over the remaining hB bits, the superset sum over y' of y.
 template <class P>
 __global__ void __launch_bounds__(kThreads)
-k_gamma_highB(int n, int d, int bG, int a, uint32_t KG, uint32_t KA, uint32_t K, Tables tb,
+k_gamma_highB(int n, int d, int a, uint32_t KA, uint32_t K, GammaGeom gg, Tables tb,
               const typename P::V *__restrict__ Y2, typename P::V *__restrict__ gam) {
     using V = typename P::V;
     const int N = n - 1;
-    const int hG = N - bG;
-    const int hB = hG - a;
-    const uint32_t vs = blockIdx.x;
-    const int v = vs / KG;
-    const uint32_t s = vs % KG;
+    const int v = find_v(gg.blkB, n, blockIdx.x);
+    const uint32_t s = blockIdx.x - gg.blkB[v];
+    const int bv = gg.bv[v], hv = gg.hv[v];
+    const int hB = hv - a;
     const int t = threadIdx.x;
     const uint32_t *bn = tb.binom;
-    const uint32_t gl = tb.seedmask[s];
-    const int sigma = __popc(gl);
+    int sigma;
+    uint32_t cl;
+    seed_of(bn, bv, s, &sigma, &cl);
     const int tr = d - sigma;
-    const uint32_t cl = s - Kcount(bn, bG, sigma - 1);
     const uint32_t ny = 1u << hB;
+    const V *base = Y2 + gg.y2off[v];
     for (uint32_t idx = t; idx < KA * ny; idx += kThreads) {
         const uint32_t pi = idx / ny;
         const uint32_t y = idx - pi * ny;
         const uint32_t p = tb.pat[pi];
         if (__popc(p) + __popc(y) > tr) continue;
-        const V *src = Y2 + (((size_t)vs * KA + pi) << hB);
+        const V *src = base + (((size_t)s * KA + pi) << hB);
         V acc = P::zero();
         const uint32_t free_bits = (ny - 1) & ~y;
-        // all supersets y' = y | sub, sub subset of free_bits, ascending
-        uint32_t sub = 0;
+        uint32_t sub = 0;   // all supersets y | sub, sub a submask of free_bits, ascending
         while (true) {
             acc = P::add(acc, src[y | sub]);
             if (sub == free_bits) break;
             sub = (sub - free_bits) & free_bits;
         }
-        const uint32_t x = p | (y << a);
-        gam[(size_t)v * K + out_rank(bn, N, sigma, cl, x, bG)] = acc;
+        gam[(size_t)v * K + out_rank(bn, N, sigma, cl, p | (y << a), bv)] = acc;
     }
 }
 
@@ -916,23 +1029,38 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     }
     rec(4);
     {
-        const int hG = N - a.bG;
-        hipLaunchKernelGGL(k_gamma_tile<P>, dim3((unsigned)(n << hG)), dim3(kThreads),
-                           sizeof(V) << a.bG, st, n, d, a.bG, a.KG, tb, L, R, (const V *)qt, Y1);
+        const GammaGeom &gg = a.gg;
+        const int bT = a.bG;
+        const size_t sm = sizeof(V) * 2 * ((size_t)1 << bT) + 33 * 33 * 4 + (size_t)gg.KT * 4 +
+                          (size_t)gg.npat * 2;
+        const dim3 g(1u << (n - bT));
+        const int RB = bT > 8 ? bT - 8 : 0;
+#define BN_GTILE(rb)                                                                           \
+    (void)hipFuncSetAttribute((const void *)k_gamma_tile<P, rb>,                               \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);            \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile<P, rb>), g, dim3(kThreads), sm, st, n, d, \
+                       bT, gg, tb, L, R, (const V *)qt, Y1)
+        switch (RB) {
+            case 0: BN_GTILE(0); break;
+            case 1: BN_GTILE(1); break;
+            case 2: BN_GTILE(2); break;
+            case 3: BN_GTILE(3); break;
+            case 4: BN_GTILE(4); break;
+            default: BN_GTILE(5); break;
+        }
+#undef BN_GTILE
         BN_CHECK_LAUNCH();
-        if (hG <= a.aG) {
-            hipLaunchKernelGGL(k_gamma_high1<P>, dim3((unsigned)(n * a.KG)), dim3(kThreads),
-                               sizeof(V) << hG, st, n, d, a.bG, a.KG, a.K, tb, (const V *)Y1,
-                               gam);
+        if (gg.blk1[n] > 0) {
+            hipLaunchKernelGGL(k_gamma_high1<P>, dim3(gg.blk1[n]), dim3(kThreads),
+                               sizeof(V) << gg.hmax1, st, n, d, a.K, gg, tb, (const V *)Y1, gam);
             BN_CHECK_LAUNCH();
-        } else {
-            const int hB = hG - a.aG;
-            hipLaunchKernelGGL(k_gamma_highA<P>, dim3((unsigned)((n * a.KG) << hB)),
-                               dim3(kThreads), sizeof(V) << a.aG, st, n, d, a.bG, a.aG, a.KG,
-                               a.KA, tb, (const V *)Y1, Y2);
+        }
+        if (gg.blkA[n] > 0) {
+            hipLaunchKernelGGL(k_gamma_highA<P>, dim3(gg.blkA[n]), dim3(kThreads),
+                               sizeof(V) << a.aG, st, n, d, a.aG, a.KA, gg, tb, (const V *)Y1, Y2);
             BN_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_gamma_highB<P>, dim3((unsigned)(n * a.KG)), dim3(kThreads), 0,
-                               st, n, d, a.bG, a.aG, a.KG, a.KA, a.K, tb, (const V *)Y2, gam);
+            hipLaunchKernelGGL(k_gamma_highB<P>, dim3(gg.blkB[n]), dim3(kThreads), 0, st, n, d,
+                               a.aG, a.KA, a.K, gg, tb, (const V *)Y2, gam);
             BN_CHECK_LAUNCH();
         }
     }

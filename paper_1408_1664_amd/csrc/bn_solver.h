@@ -23,6 +23,8 @@ struct Plan {
     uint32_t KG, KA;
     bool x32;
     int max_bins;
+    GammaGeom gg;                 // per-endpoint Gamma geometry
+    uint64_t y1_elems, y2_elems;
     std::vector<uint32_t> tiles;  // C(n - bL, h), h = 0..n-bL
     size_t o_binom, o_lorder, o_loff, o_pat, o_seed, o_famask, o_seedA, o_items, o_arity, o_rho, o_q, o_logp,
         o_beta, o_qt, o_gexp, o_alpha_f, o_alpha_b, o_L_f, o_L_b, o_R_f, o_R_b, o_Y1, o_Y2,

@@ -107,7 +107,7 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.K = (uint32_t)kcount_u64(N, d);
     P.bA = std::min(N, 13);
     P.bL = std::min(n, 10);
-    P.bG = std::min(N, 12);
+    P.bG = std::min(n, 13);
     P.aG = 12;
     // Tuning / test override "bA,bL,bG,aG" (each clamped to its valid range);
     // lets small problems exercise every tiling path.
@@ -116,16 +116,44 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
         if (sscanf(tb, "%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3]) == 4) {
             P.bA = std::max(1, std::min(std::min(v[0], N), 13));
             P.bL = std::max(2, std::min(v[1], n));
-            P.bG = std::max(1, std::min(v[2], N));
+            P.bG = std::max(1, std::min(std::min(v[2], n), 13));
             P.aG = std::max(1, std::min(v[3], 12));
         }
     }
-    const int hG = N - P.bG;
-    P.two_level = hG > P.aG;
+    // Gamma tile: the largest full-mask tile whose LDS footprint fits
+    while (P.bG > 1 && 16 * ((size_t)1 << P.bG) + 33 * 33 * 4 + 4 * kcount_u64(P.bG, d) +
+                               2 * kcount_u64(P.bG - 1, d) > 160 * 1024)
+        --P.bG;
     P.KG = (uint32_t)kcount_u64(P.bG, d);
-    P.KA = P.two_level ? (uint32_t)kcount_u64(P.aG, d) : 0;
-    P.W = std::max(std::max(P.bA, P.bG), P.two_level ? P.aG : hG);
+    P.KA = (uint32_t)kcount_u64(P.aG, d);
+    P.W = std::max(std::max(P.bA, P.bG), P.aG);
     P.W = std::max(P.W, 1);
+    {
+        GammaGeom &g = P.gg;
+        memset(&g, 0, sizeof(g));
+        uint64_t y1 = 0, y2 = 0;
+        int hmax1 = 0;
+        for (int v = 0; v < n; ++v) {
+            g.bv[v] = v < P.bG ? P.bG - 1 : P.bG;
+            g.hv[v] = N - g.bv[v];
+            const uint64_t kg = kcount_u64(g.bv[v], d);
+            g.y1off[v] = y1;
+            y1 += kg << g.hv[v];
+            const bool two = g.hv[v] > P.aG;
+            g.y2off[v] = y2;
+            if (two) y2 += (kg * P.KA) << (g.hv[v] - P.aG);
+            else hmax1 = std::max(hmax1, g.hv[v]);
+            g.blk1[v + 1] = g.blk1[v] + (two ? 0 : (uint32_t)kg);
+            g.blkA[v + 1] = g.blkA[v] + (two ? (uint32_t)(kg << (g.hv[v] - P.aG)) : 0);
+            g.blkB[v + 1] = g.blkB[v] + (two ? (uint32_t)kg : 0);
+        }
+        g.KT = P.KG;
+        g.npat = (uint32_t)kcount_u64(std::max(P.bG - 1, 0), d);
+        g.hmax1 = hmax1;
+        P.y1_elems = y1;
+        P.y2_elems = y2;
+        P.two_level = y2 > 0;
+    }
     const int nh = n - P.bL;
     P.tiles.resize(nh + 1);
     for (int h = 0; h <= nh; ++h) P.tiles[h] = (uint32_t)binom_u64(nh, h);
@@ -171,9 +199,8 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
         P.o_L_f = take(NS * 8);
         P.o_R_f = take(NS * 8);
     }
-    P.o_Y1 = take((size_t)n * P.KG * ((size_t)1 << hG) * V);
-    if (P.two_level)
-        P.o_Y2 = take((size_t)n * P.KG * P.KA * ((size_t)1 << (hG - P.aG)) * V);
+    P.o_Y1 = take((size_t)P.y1_elems * V);
+    if (P.two_level) P.o_Y2 = take((size_t)P.y2_elems * V);
     P.o_gam = take((size_t)n * P.K * V);
     P.o_part = take(((size_t)1 << nh) * (P.bL + 1) * V);
     if (with_post) P.o_post = take((size_t)n * n * 8);
@@ -276,6 +303,7 @@ bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_d
     a.diag = dev_diag ? dev_diag : reinterpret_cast<double *>(ws + P.o_diag);
     a.cnt = reinterpret_cast<unsigned long long *>(ws + P.o_cnt);
     a.tiles_per_layer = P.tiles.data();
+    a.gg = P.gg;
     hipError_t e;
     if (P.x32) {
         PolX32::Store al{reinterpret_cast<float *>(ws + P.o_alpha_f),
