@@ -37,6 +37,8 @@ struct PolLog {
         if (lo == -__builtin_huge_val()) return hi;
         return hi + log1p(exp(lo - hi));
     }
+    __device__ static inline V mul_raw(V a, V b) { return a + b; }
+    __device__ static inline V norm_v(V a) { return a; }
     __device__ static inline V from_log(double x) { return x; }
     __device__ static inline double to_log(V v) { return v; }
     // log(a / b) in FP64, a, b > 0
@@ -90,6 +92,10 @@ struct PolX32 {
         return x;
     }
     __device__ static inline V mul(V a, V b) { return norm(X32{a.f * b.f, a.e + b.e}); }
+    // Product without renormalisation (f may leave [2^-32, 2^32); add() stays
+    // exact as long as f stays within the FP32 range).
+    __device__ static inline V mul_raw(V a, V b) { return X32{a.f * b.f, a.e + b.e}; }
+    __device__ static inline V norm_v(V a) { return norm(a); }
     // Exact alignment to the larger exponent; the smaller operand is scaled
     // by an exact power of two (it underflows to zero only when it is below
     // FP32 resolution of the result).

@@ -537,19 +537,22 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
 }
 
 // ---------------------------------------- a5 + a6: Gamma, in-tile part
-// Workgroup = full-mask tile H (the low bT bits vary). L(H + x) stays in
-// registers and Rp(H + x) in LDS for the whole workgroup; every endpoint v
-// not in H is served in turn:
-//   g_v(S) = q(|S|) L(S) Rp(S + v), S = H + x, x without bit v when v is a
-//   tile bit (Rp(S + v) then sits in the same tile); for v above the tile
-//   Rp(S + v) is the tile H + v, prefetched while the previous v is reduced;
-//   truncated downward zeta over the tile bits other than v: the register
-//   bits (entry x = reg * 256 + t) densely, then the low 8 bits in LDS,
-//   where bit j only updates masks with at most d ones among the bits
-//   already processed (Def. 2; Alg. 3 predicate);
-//   the entries with at most d ones go to Y1_v[seed][Hc_v].
-// Tiles are mapped so that consecutive H run on the same XCD, which lets
-// the L2 merge the 8-byte Y1 writes of neighbouring tiles.
+// Workgroup = full-mask tile H (the low bT bits vary; entry x = reg * 256 + t).
+// L(H + x) and Rp(H + x) stay in registers for the whole workgroup; every
+// endpoint v not in H is served in turn:
+//   g_v(S) = q(|S|) L(S) Rp(S + v) for S = H + x. For v a tile bit, x runs
+//   over the entries without bit v and Rp(S + v) is the partner entry: the
+//   same thread's register when v is a register bit, else read through LDS.
+//   For v above the tile Rp(S + v) is the tile H + v, prefetched while the
+//   previous endpoint is reduced. Products are left unnormalised: the
+//   alignment in add() is exact for any FP32 significand.
+//   Truncated downward zeta over the tile bits other than v: the register
+//   bits densely, then the low 8 bits in LDS, where bit j only updates masks
+//   with at most d ones among the bits already processed (Def. 2; the
+//   predicate of Alg. 3).
+//   The entries with at most d ones go to Y1_v[seed][Hc_v].
+// Consecutive tiles run on the same XCD so that its L2 merges the 8-byte Y1
+// writes of neighbouring tiles.
 template <class P, int RB>
 __global__ void __launch_bounds__(kThreads)
 k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
@@ -559,8 +562,7 @@ k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
     constexpr int NR = 1 << RB;
     extern __shared__ unsigned char smem[];
     const uint32_t T = 1u << bT;
-    V *Rt = reinterpret_cast<V *>(smem);
-    V *gb = Rt + T;
+    V *gb = reinterpret_cast<V *>(smem);
     uint32_t *sbin = reinterpret_cast<uint32_t *>(gb + T);
     uint32_t *seedT = sbin + 33 * 33;
     uint16_t *spat = reinterpret_cast<uint16_t *>(seedT + gg.KT);
@@ -576,13 +578,15 @@ k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
     for (uint32_t x = t; x < gg.KT; x += kThreads) seedT[x] = tb.seedmask[x];
     for (uint32_t x = t; x < gg.npat; x += kThreads) spat[x] = tb.pat[x];
     if (t < n) sq[t] = qt[t];
-    V Lr[NR], Rv[NR], g[NR];
+    V Lr[NR], Rr[NR], Rv[NR], g[NR];
+    uint32_t pc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         const uint32_t x = r * kThreads + t;
+        pc[r] = __popcll(Hf | x);
         if (x < T) {
             Lr[r] = P::load(L, Hf | x);
-            Rt[x] = P::load(R, Hf | x);
+            Rr[r] = P::load(R, Hf | x);
         }
     }
     int vn = bT;                              // next endpoint above the tile, not in H
@@ -599,19 +603,48 @@ k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
     for (int v = 0; v < n; ++v) {
         const bool low = v < bT;
         if (!low && ((Hf >> v) & 1)) continue;
+        if (low && v < lb) {
+            // partner Rp(S + v) lives in another thread: exchange through LDS
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const uint32_t x = r * kThreads + t;
-            if (x >= T) continue;
-            if (low && ((x >> v) & 1)) {
-                g[r] = P::zero();
-                continue;
+            for (int r = 0; r < NR; ++r) {
+                const uint32_t x = r * kThreads + t;
+                if (x < T) gb[x] = Rr[r];
             }
-            const V q = sq[__popcll(Hf | x)];   // |S| <= n-1 since v is not in S
-            g[r] = P::mul(q, P::mul(Lr[r], low ? Rt[x | (1u << v)] : Rv[r]));
-        }
-        if (!low) {                           // prefetch the next endpoint's Rp tile
-            vn = v + 1;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const uint32_t x = r * kThreads + t;
+                if (x >= T) continue;
+                if ((x >> v) & 1) {
+                    g[r] = P::zero();
+                } else {
+                    g[r] = P::mul_raw(sq[pc[r]], P::mul_raw(Lr[r], gb[x | (1u << v)]));
+                }
+            }
+            __syncthreads();
+        } else if (low) {
+            // v is register bit q: the partner is register r + 2^q of this thread
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                if (v - lb != q) continue;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    if ((r >> q) & 1) {
+                        g[r] = P::zero();
+                    } else {
+                        const uint32_t x = r * kThreads + t;
+                        if (x < T)
+                            g[r] = P::mul_raw(sq[pc[r]], P::mul_raw(Lr[r], Rr[r | (1 << q)]));
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const uint32_t x = r * kThreads + t;
+                if (x < T) g[r] = P::mul_raw(sq[pc[r]], P::mul_raw(Lr[r], Rv[r]));
+            }
+            vn = v + 1;                       // prefetch the next endpoint's Rp tile
             while (vn < n && ((Hf >> vn) & 1)) ++vn;
             if (vn < n) {
 #pragma unroll
@@ -638,14 +671,12 @@ k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
         // thread bits in LDS, truncated on the bits already processed
         for (int j = 0; j < lb; ++j) {
             if (j == v) continue;
-            const uint32_t np = Kcount(bn, j + RB, d);
-            const uint32_t nfree = 1u << (lb - 1 - j);
-            const uint32_t cnt = np * nfree;
+            const int fb = lb - 1 - j;           // free bits above j
+            const uint32_t cnt = Kcount(bn, j + RB, d) << fb;
+            const uint32_t jm = (1u << j) - 1, fm = (1u << fb) - 1;
             for (uint32_t idx = t; idx < cnt; idx += kThreads) {
-                const uint32_t pi = idx / nfree;
-                const uint32_t f = idx - pi * nfree;
-                const uint32_t p = spat[pi];
-                const uint32_t Tm = (p & ((1u << j) - 1)) | ((p >> j) << lb) | (f << (j + 1));
+                const uint32_t p = spat[idx >> fb];
+                const uint32_t Tm = (p & jm) | ((p >> j) << lb) | ((idx & fm) << (j + 1));
                 gb[Tm] = P::add(gb[Tm], gb[Tm | (1u << j)]);
             }
             __syncthreads();
@@ -670,7 +701,7 @@ k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
                     rank += C(bn, p, ++k);
                 }
             }
-            dst[((size_t)rank << hv) + Hc] = gb[msk];
+            dst[((size_t)rank << hv) + Hc] = P::norm_v(gb[msk]);
         }
         __syncthreads();
     }
@@ -1031,7 +1062,7 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     {
         const GammaGeom &gg = a.gg;
         const int bT = a.bG;
-        const size_t sm = sizeof(V) * 2 * ((size_t)1 << bT) + 33 * 33 * 4 + (size_t)gg.KT * 4 +
+        const size_t sm = sizeof(V) * ((size_t)1 << bT) + 33 * 33 * 4 + (size_t)gg.KT * 4 +
                           (size_t)gg.npat * 2;
         const dim3 g(1u << (n - bT));
         const int RB = bT > 8 ? bT - 8 : 0;
