@@ -39,6 +39,23 @@ struct PolLog {
     }
     __device__ static inline V mul_raw(V a, V b) { return a + b; }
     __device__ static inline V norm_v(V a) { return a; }
+    // Undecoded HBM value: lets loads be issued long before their use.
+    using Raw = double;
+    __device__ static inline Raw load_raw(const Store &s, uint64_t i) { return s.p[i]; }
+    __device__ static inline V decode_raw(Raw r) { return r; }
+    struct Raw4 {
+        double2 a, b;
+    };
+    __device__ static inline Raw4 load4_raw(const Store &s, uint64_t i) {
+        return Raw4{*reinterpret_cast<const double2 *>(s.p + i),
+                    *reinterpret_cast<const double2 *>(s.p + i + 2)};
+    }
+    __device__ static inline void decode4(const Raw4 &r, V *o) {
+        o[0] = r.a.x;
+        o[1] = r.a.y;
+        o[2] = r.b.x;
+        o[3] = r.b.y;
+    }
     __device__ static inline V from_log(double x) { return x; }
     __device__ static inline double to_log(V v) { return v; }
     // log(a / b) in FP64, a, b > 0
@@ -120,6 +137,29 @@ struct PolX32 {
     }
     __device__ static inline V load(const Store &s, uint64_t i) {
         return decode(s.f[i], s.b[i]);
+    }
+    // Undecoded HBM value: lets loads be issued long before their use.
+    struct Raw {
+        float f;
+        uint32_t b;
+    };
+    __device__ static inline Raw load_raw(const Store &s, uint64_t i) {
+        return Raw{s.f[i], (uint32_t)s.b[i]};
+    }
+    __device__ static inline V decode_raw(Raw r) { return decode(r.f, (int)r.b); }
+    struct Raw4 {
+        float4 f;
+        uint32_t b;
+    };
+    __device__ static inline Raw4 load4_raw(const Store &s, uint64_t i) {
+        return Raw4{*reinterpret_cast<const float4 *>(s.f + i),
+                    *reinterpret_cast<const uint32_t *>(s.b + i)};
+    }
+    __device__ static inline void decode4(const Raw4 &r, V *o) {
+        o[0] = decode(r.f.x, r.b & 0xff);
+        o[1] = decode(r.f.y, (r.b >> 8) & 0xff);
+        o[2] = decode(r.f.z, (r.b >> 16) & 0xff);
+        o[3] = decode(r.f.w, r.b >> 24);
     }
     // Encode one value: returns the byte, writes the significand to *f.
     // cnt[0] counts saturations, cnt[1] flushes of nonzero values.

@@ -296,22 +296,41 @@ k_alpha(int n, int d, uint32_t K, int bA, Tables tb, const typename P::V *__rest
                 int k = 0;
                 uint32_t klo = 0, khi = 1;          // items of size k: [klo, khi)
                 uint32_t toff = 0;                  // item-table offset of size k
-                for (uint32_t it = lane; it < items; it += grp) {
-                    while (it >= khi) {
-                        toff += C(bn, hA, k);
-                        ++k;
-                        klo = khi;
-                        khi += C(bn, h, k);
+                constexpr int B = 4;                // items per batch of loads
+                for (uint32_t it0 = lane; it0 < items; it0 += B * grp) {
+                    uint32_t msk[B], sz[B];
+#pragma unroll
+                    for (int u = 0; u < B; ++u) {
+                        const uint32_t it = it0 + u * grp;
+                        if (it < items) {
+                            while (it >= khi) {
+                                toff += C(bn, hA, k);
+                                ++k;
+                                klo = khi;
+                                khi += C(bn, h, k);
+                            }
+                            msk[u] = tb.items[toff + (it - klo)];
+                            sz[u] = k;
+                        }
                     }
-                    uint32_t m = tb.items[toff + (it - klo)];
-                    uint32_t rank = offN[s + k] + seed;
-                    int q = 0;
-                    while (m) {
-                        const int e = __ffs(m) - 1;
-                        m &= m - 1;
-                        rank += C(bn, hb[e], s + (++q));
+                    typename P::V bv[B];
+#pragma unroll
+                    for (int u = 0; u < B; ++u) {
+                        if (it0 + u * grp < items) {
+                            uint32_t m = msk[u];
+                            uint32_t rank = offN[s + sz[u]] + seed;
+                            int q = 0;
+                            while (m) {
+                                const int e = __ffs(m) - 1;
+                                m &= m - 1;
+                                rank += C(bn, hb[e], s + (++q));
+                            }
+                            bv[u] = bi[rank];
+                        }
                     }
-                    acc = P::add(acc, bi[rank]);
+#pragma unroll
+                    for (int u = 0; u < B; ++u)
+                        if (it0 + u * grp < items) acc = P::add(acc, bv[u]);
                 }
             }
             for (int w = grp / 2; w > 0; w >>= 1) acc = P::add(acc, shfl_xor_v(acc, w));
@@ -356,12 +375,76 @@ k_alpha(int n, int d, uint32_t K, int bA, Tables tb, const typename P::V *__rest
     }
 }
 
+// ------------------------------------------- a3/a4: sweep helpers
+// Stage alpha_i(Hf + Lo') (Lo' without bit i) for the bL tile bits into LDS:
+// slice i is the contiguous block alpha_i[(Hf >> 1) + k], k < 2^(bL-1).
+// All loads of a thread are issued before any is decoded.
+template <class P>
+__device__ inline void stage_alpha(const typename P::Store &alpha, uint64_t NN, uint64_t Hf,
+                                   int bL, typename P::V *la) {
+    using V = typename P::V;
+    const uint32_t half = 1u << (bL - 1);
+    const uint32_t total = (uint32_t)bL * half;
+    const int t = threadIdx.x;
+    if (half >= 4) {
+        constexpr int U = 5;                  // 10 * 512 / (4 * 256) for bL = 10
+        for (uint32_t e0 = 4 * t; e0 < total; e0 += 4 * kThreads * U) {
+            typename P::Raw4 raw[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t e = e0 + 4 * kThreads * u;
+                if (e < total)
+                    raw[u] = P::load4_raw(alpha, (uint64_t)(e >> (bL - 1)) * NN + (Hf >> 1) +
+                                                     (e & (half - 1)));
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t e = e0 + 4 * kThreads * u;
+                if (e < total) P::decode4(raw[u], la + e);
+            }
+        }
+    } else {
+        for (uint32_t e = t; e < total; e += kThreads)
+            la[e] = P::load(alpha, (uint64_t)(e >> (bL - 1)) * NN + (Hf >> 1) + (e & (half - 1)));
+    }
+}
+
+// acc[k] += sum over the listed nodes i of alpha_i[ai(i) + k] * X[xi(i) + k], k < 4,
+// four nodes per batch of loads.
+template <class P, class AI, class XI>
+__device__ inline void cross_terms(const typename P::Store &alpha, const typename P::Store &X,
+                                   const int *nodes, int cnt, AI ai, XI xi, typename P::V *acc) {
+    using V = typename P::V;
+    constexpr int B = 4;
+    for (int q0 = 0; q0 < cnt; q0 += B) {
+        typename P::Raw4 ra[B], rx[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (q0 + u < cnt) {
+                const int i = nodes[q0 + u];
+                ra[u] = P::load4_raw(alpha, ai(i));
+                rx[u] = P::load4_raw(X, xi(i));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (q0 + u < cnt) {
+                V a[4], x[4];
+                P::decode4(ra[u], a);
+                P::decode4(rx[u], x);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[k] = P::add(acc[k], P::mul(a[k], x[k]));
+            }
+        }
+    }
+}
+
 // ------------------------------------------- a3: forward sweep, one layer
 // Workgroup = tile H with |H| = h (H over the n-bL high bits). Cross-tile
 // terms (i in H) stream contiguous 2^bL blocks of alpha_i and L, four
-// consecutive entries per thread, two nodes per iteration; in-tile terms (i
-// among the low bits) use the tile's alpha slices staged in LDS and run
-// popcount layer by popcount layer. Requires bL >= 2.
+// consecutive entries per thread; in-tile terms (i among the low bits) use
+// the tile's alpha slices staged in LDS and run popcount layer by popcount
+// layer. Requires bL >= 2.
 template <class P>
 __global__ void __launch_bounds__(kThreads)
 k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Store L,
@@ -377,49 +460,24 @@ k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
     __shared__ int pos[32];
     const int t = threadIdx.x;
     const uint64_t NN = 1ull << (n - 1);
-    if (t == 0) colex_unrank(tb.binom, blockIdx.x, h, pos);
+    if (t == 0) {
+        colex_unrank(tb.binom, blockIdx.x, h, pos);
+        for (int q = 0; q < h; ++q) pos[q] += bL;   // node indices of H
+    }
     if (t < bL + 2) loff[t] = tb.loff[t];
     for (uint32_t x = t; x < T; x += kThreads) lord[x] = tb.lorder[x];
     __syncthreads();
     uint64_t Hf = 0;
-    for (int q = 0; q < h; ++q) Hf |= 1ull << (bL + pos[q]);
-    // stage the in-tile alpha slices: alpha_i(Hf + Lo'), Lo' without i
-    for (int i = 0; i < bL; ++i) {
-        const uint64_t src = (uint64_t)i * NN + (Hf >> 1);
-        if (half >= 4) {
-            for (uint32_t k = 4 * t; k < half; k += 4 * kThreads)
-                P::load4(alpha, src + k, la + i * half + k);
-        } else {
-            for (uint32_t k = t; k < half; k += kThreads) la[i * half + k] = P::load(alpha, src + k);
-        }
-    }
-    // cross-tile terms
+    for (int q = 0; q < h; ++q) Hf |= 1ull << pos[q];
+    stage_alpha<P>(alpha, NN, Hf, bL, la);
+    // cross-tile terms: alpha_i(S - i) L(S - i) for i in H
     for (uint32_t lo = 4 * t; lo < T; lo += 4 * kThreads) {
         V acc[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[k] = (Hf == 0 && lo + k == 0) ? P::one() : P::zero();
-        int q = 0;
-        for (; q + 1 < h; q += 2) {
-            const int i0 = bL + pos[q], i1 = bL + pos[q + 1];
-            const uint64_t S0 = (Hf ^ (1ull << i0)) | lo, S1 = (Hf ^ (1ull << i1)) | lo;
-            V a0[4], l0[4], a1[4], l1[4];
-            P::load4(alpha, (uint64_t)i0 * NN + compress_bit(S0, i0), a0);
-            P::load4(L, S0, l0);
-            P::load4(alpha, (uint64_t)i1 * NN + compress_bit(S1, i1), a1);
-            P::load4(L, S1, l1);
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                acc[k] = P::add(acc[k], P::add(P::mul(a0[k], l0[k]), P::mul(a1[k], l1[k])));
-        }
-        if (q < h) {
-            const int i0 = bL + pos[q];
-            const uint64_t S0 = (Hf ^ (1ull << i0)) | lo;
-            V a0[4], l0[4];
-            P::load4(alpha, (uint64_t)i0 * NN + compress_bit(S0, i0), a0);
-            P::load4(L, S0, l0);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) acc[k] = P::add(acc[k], P::mul(a0[k], l0[k]));
-        }
+        cross_terms<P>(alpha, L, pos, h,
+                       [&](int i) { return (uint64_t)i * NN + compress_bit((Hf ^ (1ull << i)) | lo, i); },
+                       [&](int i) { return (Hf ^ (1ull << i)) | lo; }, acc);
 #pragma unroll
         for (int k = 0; k < 4; ++k) lt[lo + k] = acc[k];
     }
@@ -469,7 +527,7 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
         for (int q = 0; q < h; ++q) Hm |= 1u << pos[q];
         int no = 0;
         for (int p = 0; p < nh; ++p)
-            if (!((Hm >> p) & 1)) outs[no++] = bL + p;
+            if (!((Hm >> p) & 1)) outs[no++] = bL + p;   // nodes above the tile, not in H
         nout_s = no;
     }
     if (t < bL + 2) loff[t] = tb.loff[t];
@@ -479,41 +537,16 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
     for (int q = 0; q < h; ++q) Hf |= 1ull << (bL + pos[q]);
     const int nout = nout_s;
     const uint64_t highall = ((1ull << nh) - 1) << bL;
-    for (int i = 0; i < bL; ++i) {
-        const uint64_t src = (uint64_t)i * NN + (Hf >> 1);
-        if (half >= 4) {
-            for (uint32_t k = 4 * t; k < half; k += 4 * kThreads)
-                P::load4(alpha, src + k, la + i * half + k);
-        } else {
-            for (uint32_t k = t; k < half; k += kThreads) la[i * half + k] = P::load(alpha, src + k);
-        }
-    }
+    stage_alpha<P>(alpha, NN, Hf, bL, la);
     for (uint32_t lo = 4 * t; lo < T; lo += 4 * kThreads) {
         V acc[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             acc[k] = (Hf == highall && lo + k == T - 1) ? P::one() : P::zero();
         const uint64_t Sm = Hf | lo;
-        int q = 0;
-        for (; q + 1 < nout; q += 2) {
-            const int i0 = outs[q], i1 = outs[q + 1];
-            V a0[4], r0[4], a1[4], r1[4];
-            P::load4(alpha, (uint64_t)i0 * NN + compress_bit(Sm, i0), a0);
-            P::load4(R, Sm | (1ull << i0), r0);
-            P::load4(alpha, (uint64_t)i1 * NN + compress_bit(Sm, i1), a1);
-            P::load4(R, Sm | (1ull << i1), r1);
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                acc[k] = P::add(acc[k], P::add(P::mul(a0[k], r0[k]), P::mul(a1[k], r1[k])));
-        }
-        if (q < nout) {
-            const int i0 = outs[q];
-            V a0[4], r0[4];
-            P::load4(alpha, (uint64_t)i0 * NN + compress_bit(Sm, i0), a0);
-            P::load4(R, Sm | (1ull << i0), r0);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) acc[k] = P::add(acc[k], P::mul(a0[k], r0[k]));
-        }
+        cross_terms<P>(alpha, R, outs, nout,
+                       [&](int i) { return (uint64_t)i * NN + compress_bit(Sm, i); },
+                       [&](int i) { return Sm | (1ull << i); }, acc);
 #pragma unroll
         for (int k = 0; k < 4; ++k) lt[lo + k] = acc[k];
     }
@@ -578,15 +611,26 @@ k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
     for (uint32_t x = t; x < gg.KT; x += kThreads) seedT[x] = tb.seedmask[x];
     for (uint32_t x = t; x < gg.npat; x += kThreads) spat[x] = tb.pat[x];
     if (t < n) sq[t] = qt[t];
-    V Lr[NR], Rr[NR], Rv[NR], g[NR];
+    using Raw = typename P::Raw;
+    V Lr[NR], Rr[NR], g[NR];
+    Raw Rv[NR];                               // next endpoint's Rp tile, undecoded
     uint32_t pc[NR];
+    const bool full = RB > 0 || T >= kThreads;   // every (r, t) maps to an entry
+    {
+        Raw l0[NR], r0[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const uint32_t x = r * kThreads + t;
-        pc[r] = __popcll(Hf | x);
-        if (x < T) {
-            Lr[r] = P::load(L, Hf | x);
-            Rr[r] = P::load(R, Hf | x);
+        for (int r = 0; r < NR; ++r) {
+            const uint32_t x = r * kThreads + t;
+            pc[r] = __popcll(Hf | x);
+            if (full || x < T) {
+                l0[r] = P::load_raw(L, Hf | x);
+                r0[r] = P::load_raw(R, Hf | x);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            Lr[r] = P::decode_raw(l0[r]);
+            Rr[r] = P::decode_raw(r0[r]);
         }
     }
     int vn = bT;                              // next endpoint above the tile, not in H
@@ -595,7 +639,7 @@ k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const uint32_t x = r * kThreads + t;
-            if (x < T) Rv[r] = P::load(R, Hf | x | (1ull << vn));
+            if (full || x < T) Rv[r] = P::load_raw(R, Hf | x | (1ull << vn));
         }
     }
     __syncthreads();
@@ -608,13 +652,13 @@ k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 const uint32_t x = r * kThreads + t;
-                if (x < T) gb[x] = Rr[r];
+                if (full || x < T) gb[x] = Rr[r];
             }
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 const uint32_t x = r * kThreads + t;
-                if (x >= T) continue;
+                if (!full && x >= T) continue;
                 if ((x >> v) & 1) {
                     g[r] = P::zero();
                 } else {
@@ -633,7 +677,7 @@ k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
                         g[r] = P::zero();
                     } else {
                         const uint32_t x = r * kThreads + t;
-                        if (x < T)
+                        if (full || x < T)
                             g[r] = P::mul_raw(sq[pc[r]], P::mul_raw(Lr[r], Rr[r | (1 << q)]));
                     }
                 }
@@ -642,7 +686,8 @@ k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 const uint32_t x = r * kThreads + t;
-                if (x < T) g[r] = P::mul_raw(sq[pc[r]], P::mul_raw(Lr[r], Rv[r]));
+                if (full || x < T)
+                    g[r] = P::mul_raw(sq[pc[r]], P::mul_raw(Lr[r], P::decode_raw(Rv[r])));
             }
             vn = v + 1;                       // prefetch the next endpoint's Rp tile
             while (vn < n && ((Hf >> vn) & 1)) ++vn;
@@ -650,7 +695,7 @@ k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
                     const uint32_t x = r * kThreads + t;
-                    if (x < T) Rv[r] = P::load(R, Hf | x | (1ull << vn));
+                    if (full || x < T) Rv[r] = P::load_raw(R, Hf | x | (1ull << vn));
                 }
             }
         }
@@ -665,7 +710,7 @@ k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const uint32_t x = r * kThreads + t;
-            if (x < T) gb[x] = g[r];
+            if (full || x < T) gb[x] = g[r];
         }
         __syncthreads();
         // thread bits in LDS, truncated on the bits already processed
