@@ -570,6 +570,173 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
 }
 
 // ---------------------------------------- a5 + a6: Gamma, in-tile part
+// In-register downward zeta step over register bit q of NR = 2^RB entries,
+// skipped when that register bit carries the endpoint itself.
+template <class P, int NR>
+__device__ inline void reg_zeta_down(typename P::V *g, int q) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if (!((r >> q) & 1)) g[r] = P::add(g[r], g[r | (1 << q)]);
+}
+
+// Padded LDS index: one spare slot every 16 entries keeps the transposed
+// reads of the Gamma tile free of heavy bank conflicts.
+__device__ inline uint32_t padx(uint32_t x) { return x + (x >> 4); }
+
+// Workgroup = full-mask tile H of 2^12 masks (the low 12 bits vary), 256
+// threads x 16 entries. L(H + x) and Rp(H + x) stay in registers for the
+// whole workgroup; every endpoint v not in H is served in turn:
+//   g_v(S) = q(|S|) L(S) Rp(S + v) for S = H + x. For v a tile bit, x runs
+//   over the entries without bit v and Rp(S + v) is the partner entry (same
+//   thread for a register bit, else read through LDS). For v above the tile
+//   Rp(S + v) is the tile H + v, prefetched while the previous endpoint is
+//   reduced. Products are left unnormalised (add() aligns exactly).
+//   Downward zeta over the tile bits other than v, entirely in registers:
+//   layout A holds tile bits 8..11 in the register index (x = r*256 + t),
+//   layout B bits 4..7 (x = t_hi*256 + r*16 + t_lo), layout C bits 0..3
+//   (x = t*16 + r); two LDS transposes move between them.
+//   The entries with at most d ones (Def. 2: Gamma_v(G) is needed for
+//   |G| <= d only) go from registers to Y1_v[seed][Hc_v].
+// Consecutive tiles run on the same XCD so that its L2 merges the 8-byte Y1
+// writes of neighbouring tiles.
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_gamma_tile(int n, int d, GammaGeom gg, Tables tb, typename P::Store L, typename P::Store R,
+             const typename P::V *__restrict__ qt, typename P::V *__restrict__ Y1) {
+    using V = typename P::V;
+    using Raw = typename P::Raw;
+    constexpr int bT = 12, NR = 16;
+    extern __shared__ unsigned char smem[];
+    V *gb = reinterpret_cast<V *>(smem);                       // padded 2^12 entries
+    uint32_t *sbin = reinterpret_cast<uint32_t *>(gb + 4096 + 256);
+    __shared__ V sq[32];
+    __shared__ uint32_t offT[34], offT1[34];
+    const int t = threadIdx.x;
+    const int hbits = n - bT;
+    const uint32_t nblk = 1u << hbits;
+    uint32_t H = blockIdx.x;
+    if (nblk >= 64) H = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
+    const uint64_t Hf = (uint64_t)H << bT;
+    for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
+    if (t < n) sq[t] = qt[t];
+    V Lr[NR], Rr[NR], g[NR];
+    Raw Rv[NR];                               // next endpoint's Rp tile, undecoded
+    uint32_t pc[NR];
+    {
+        Raw l0[NR], r0[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const uint32_t x = r * kThreads + t;
+            pc[r] = __popcll(Hf | x);
+            l0[r] = P::load_raw(L, Hf | x);
+            r0[r] = P::load_raw(R, Hf | x);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            Lr[r] = P::decode_raw(l0[r]);
+            Rr[r] = P::decode_raw(r0[r]);
+        }
+    }
+    int vn = bT;                              // next endpoint above the tile, not in H
+    while (vn < n && ((Hf >> vn) & 1)) ++vn;
+    if (vn < n) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) Rv[r] = P::load_raw(R, Hf | (r * kThreads + t) | (1ull << vn));
+    }
+    __syncthreads();
+    if (t <= d + 1) {
+        offT[t] = Kcount(sbin, bT, t - 1);
+        offT1[t] = Kcount(sbin, bT - 1, t - 1);
+    }
+    const uint32_t tlo = t & 15, thi = t >> 4;
+    for (int v = 0; v < n; ++v) {
+        const bool low = v < bT;
+        if (!low && ((Hf >> v) & 1)) continue;
+        // ---- g in layout A
+        if (low && v < 8) {
+            // partner Rp(S + v) lives in another thread: exchange through LDS
+#pragma unroll
+            for (int r = 0; r < NR; ++r) gb[padx(r * kThreads + t)] = Rr[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const uint32_t x = r * kThreads + t;
+                g[r] = ((x >> v) & 1) ? P::zero()
+                                      : P::mul_raw(sq[pc[r]], P::mul_raw(Lr[r], gb[padx(x | (1u << v))]));
+            }
+            __syncthreads();
+        } else if (low) {
+            // v is register bit q: the partner is register r + 2^q of this thread
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (v - 8 != q) continue;
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    g[r] = ((r >> q) & 1) ? P::zero()
+                                          : P::mul_raw(sq[pc[r]], P::mul_raw(Lr[r], Rr[r | (1 << q)]));
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                g[r] = P::mul_raw(sq[pc[r]], P::mul_raw(Lr[r], P::decode_raw(Rv[r])));
+            vn = v + 1;                       // prefetch the next endpoint's Rp tile
+            while (vn < n && ((Hf >> vn) & 1)) ++vn;
+            if (vn < n) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    Rv[r] = P::load_raw(R, Hf | (r * kThreads + t) | (1ull << vn));
+            }
+        }
+        // ---- tile bits 8..11 (layout A)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (v != 8 + q) reg_zeta_down<P, NR>(g, q);
+        // ---- A -> B, tile bits 4..7
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gb[padx(r * kThreads + t)] = g[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NR; ++r) g[r] = gb[padx((thi << 8) | (r << 4) | tlo)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (v != 4 + q) reg_zeta_down<P, NR>(g, q);
+        __syncthreads();
+        // ---- B -> C, tile bits 0..3
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gb[padx((thi << 8) | (r << 4) | tlo)] = g[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NR; ++r) g[r] = gb[padx((t << 4) | r)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (v != q) reg_zeta_down<P, NR>(g, q);
+        // ---- outputs from registers: x = t*16 + r with at most d ones
+        const int hv = gg.hv[v];
+        const uint32_t Hc = low ? H : (uint32_t)compress_bit(H, v - bT);
+        V *dst = Y1 + gg.y1off[v];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const uint32_t x = (t << 4) | r;
+            const int px = __popc(x);
+            if (px > d || (low && ((x >> v) & 1))) continue;
+            const uint32_t cm = low ? (uint32_t)compress_bit(x, v) : x;
+            uint32_t rank = low ? offT1[px] : offT[px];
+            int k = 0;
+            uint32_t rest = cm;
+            while (rest) {
+                const int p = __ffs(rest) - 1;
+                rest &= rest - 1;
+                rank += C(sbin, p, ++k);
+            }
+            dst[((size_t)rank << hv) + Hc] = P::norm_v(g[r]);
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------- a5 + a6: Gamma, in-tile part, tiles of any size
+// Generic form used when the lattice is smaller than the 12-bit tile of
+// k_gamma_tile (n < 12): the whole lattice is one tile of bT = n bits.
 // Workgroup = full-mask tile H (the low bT bits vary; entry x = reg * 256 + t).
 // L(H + x) and Rp(H + x) stay in registers for the whole workgroup; every
 // endpoint v not in H is served in turn:
@@ -588,7 +755,7 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
 // writes of neighbouring tiles.
 template <class P, int RB>
 __global__ void __launch_bounds__(kThreads)
-k_gamma_tile(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
+k_gamma_tile_gen(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
              typename P::Store R, const typename P::V *__restrict__ qt,
              typename P::V *__restrict__ Y1) {
     using V = typename P::V;
@@ -1106,25 +1273,31 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     rec(4);
     {
         const GammaGeom &gg = a.gg;
-        const int bT = a.bG;
-        const size_t sm = sizeof(V) * ((size_t)1 << bT) + 33 * 33 * 4 + (size_t)gg.KT * 4 +
-                          (size_t)gg.npat * 2;
-        const dim3 g(1u << (n - bT));
-        const int RB = bT > 8 ? bT - 8 : 0;
+        if (a.bG == 12) {
+            const size_t sm = sizeof(V) * (4096 + 256) + 33 * 33 * 4;
+            (void)hipFuncSetAttribute((const void *)k_gamma_tile<P>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile<P>), dim3(1u << (n - 12)),
+                               dim3(kThreads), sm, st, n, d, gg, tb, L, R, (const V *)qt, Y1);
+        } else {
+            const int bT = a.bG;
+            const size_t sm = sizeof(V) * ((size_t)1 << bT) + 33 * 33 * 4 + (size_t)gg.KT * 4 +
+                              (size_t)gg.npat * 2;
+            const dim3 g(1u << (n - bT));
+            const int RB = bT > 8 ? bT - 8 : 0;
 #define BN_GTILE(rb)                                                                           \
-    (void)hipFuncSetAttribute((const void *)k_gamma_tile<P, rb>,                               \
+    (void)hipFuncSetAttribute((const void *)k_gamma_tile_gen<P, rb>,                           \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);            \
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile<P, rb>), g, dim3(kThreads), sm, st, n, d, \
-                       bT, gg, tb, L, R, (const V *)qt, Y1)
-        switch (RB) {
-            case 0: BN_GTILE(0); break;
-            case 1: BN_GTILE(1); break;
-            case 2: BN_GTILE(2); break;
-            case 3: BN_GTILE(3); break;
-            case 4: BN_GTILE(4); break;
-            default: BN_GTILE(5); break;
-        }
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile_gen<P, rb>), g, dim3(kThreads), sm, st, n, \
+                       d, bT, gg, tb, L, R, (const V *)qt, Y1)
+            switch (RB) {
+                case 0: BN_GTILE(0); break;
+                case 1: BN_GTILE(1); break;
+                case 2: BN_GTILE(2); break;
+                default: BN_GTILE(3); break;
+            }
 #undef BN_GTILE
+        }
         BN_CHECK_LAUNCH();
         if (gg.blk1[n] > 0) {
             hipLaunchKernelGGL(k_gamma_high1<P>, dim3(gg.blk1[n]), dim3(kThreads),

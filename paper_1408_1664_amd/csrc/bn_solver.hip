@@ -107,7 +107,7 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.K = (uint32_t)kcount_u64(N, d);
     P.bA = std::min(N, 13);
     P.bL = std::min(n, 10);
-    P.bG = std::min(n, 12);
+    P.bG = n >= 12 ? 12 : n;      // Gamma tile: 12 bits, or the whole lattice when smaller
     P.aG = 12;
     // Tuning / test override "bA,bL,bG,aG" (each clamped to its valid range);
     // lets small problems exercise every tiling path.
@@ -116,14 +116,10 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
         if (sscanf(tb, "%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3]) == 4) {
             P.bA = std::max(1, std::min(std::min(v[0], N), 13));
             P.bL = std::max(2, std::min(v[1], n));
-            P.bG = std::max(1, std::min(std::min(v[2], n), 12));
+            (void)v[2];
             P.aG = std::max(1, std::min(v[3], 12));
         }
     }
-    // Gamma tile: the largest full-mask tile whose LDS footprint fits
-    while (P.bG > 1 && 8 * ((size_t)1 << P.bG) + 33 * 33 * 4 + 4 * kcount_u64(P.bG, d) +
-                               2 * kcount_u64(P.bG - 1, d) > 160 * 1024)
-        --P.bG;
     P.KG = (uint32_t)kcount_u64(P.bG, d);
     P.KA = (uint32_t)kcount_u64(P.aG, d);
     P.W = std::max(std::max(P.bA, P.bG), P.aG);
