@@ -237,53 +237,98 @@ __device__ inline X32 shfl_xor_v(X32 v, int m) {
     return X32{__shfl_xor(v.f, m), __shfl_xor(v.e, m)};
 }
 
+// Padded LDS index for 2^13-entry tiles: one spare slot every 32 entries
+// keeps the transposed accesses of the alpha tile nearly free of bank
+// conflicts.
+__device__ inline uint32_t pad32(uint32_t x) { return x + (x >> 5); }
+
+template <class P, int NR>
+__device__ inline void reg_zeta_up(typename P::V *v, int q) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if ((r >> q) & 1) v[r] = P::add(v[r], v[r ^ (1 << q)]);
+}
+
 // Workgroup (i, H): the tile of node i's lattice (n-1 bits) whose high
-// N-bA bits are H; tile entry x = the low bA bits.
-//  1. Seeds Z(G_L) = sum_{G_H subset H, |G_H| <= d-|G_L|} beta_i(G_H + G_L) for
-//     every |G_L| <= d. The (seed, G_H) items are enumerated from a ranked
-//     table of small masks over the high bits; each seed is summed by a group
-//     of lanes of one wavefront and reduced by cross-lane shuffles.
-//  2. Truncated upward zeta over the low 8 bits in LDS: at bit j only masks
-//     with at most d ones above j can be nonzero (Def. 1; Alg. 2 predicate).
-//  3. The remaining RB = bA-8 bits in registers (entry x = reg * 256 + t),
-//     then alpha = q(|S|) * t(S), stored coalesced.
-template <class P, int RB>
+// N-13 bits are H; tile entry x = the low 13 bits, 256 threads x 32 entries.
+//  1. Seeds Z(G_L) = sum_{G_H subset H, |G_H| <= d-|G_L|} beta_i(G_H + G_L)
+//     for every |G_L| <= d. The G_H are the small masks over H's bits (a
+//     ranked table); their contribution to the rank of G_L + G_H is
+//     tabulated once per workgroup, so a (seed, G_H) pair costs one LDS
+//     read and one beta gather. Each seed is summed by a group of lanes and
+//     reduced by cross-lane shuffles.
+//  2. Upward zeta over the 13 tile bits in registers, in three layouts:
+//     bits 0..4 (thread t holds x = ord8[t]*32 + r; ord8 lists the 8-bit
+//     patterns by popcount, so the waves whose entries are all structural
+//     zeros -- more than d ones above bit 4, Def. 1 -- skip it), bits 5..9
+//     and bits 10..12 (x = r*256 + t), with two LDS transposes.
+//  3. alpha = q(|S|) * t(S), stored coalesced from the last layout.
+template <class P>
 __global__ void __launch_bounds__(kThreads)
-k_alpha(int n, int d, uint32_t K, int bA, Tables tb, const typename P::V *__restrict__ beta,
+k_alpha(int n, int d, uint32_t K, int use_prk, Tables tb, const typename P::V *__restrict__ beta,
         const typename P::V *__restrict__ qt, typename P::Store alpha,
         unsigned long long *cnt) {
     using V = typename P::V;
+    constexpr int bA = 13, NR = 32;
     extern __shared__ unsigned char smem[];
-    V *tile = reinterpret_cast<V *>(smem);                     // 2^bA
-    uint32_t *sbin = reinterpret_cast<uint32_t *>(tile + (1u << bA));  // 33 x 33
-    uint16_t *spat = reinterpret_cast<uint16_t *>(sbin + 33 * 33);    // K(bA-1, d)
+    V *tile = reinterpret_cast<V *>(smem);                         // pad32(2^13)
+    uint32_t *sbin = reinterpret_cast<uint32_t *>(tile + 8192 + 256);
+    uint16_t *prk = reinterpret_cast<uint16_t *>(sbin + 33 * 33);  // (d+1) x items
     __shared__ int hb[32];
     __shared__ uint32_t offN[34];
     __shared__ V sq[32];
+    __shared__ uint8_t ord8[256];
     const int N = n - 1;
     const int hA = N - bA;
     const int i = blockIdx.x >> hA;
     const uint32_t H = blockIdx.x & ((1u << hA) - 1);
     const int t = threadIdx.x;
     for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
-    const uint32_t npat = Kcount(tb.binom, bA > 0 ? bA - 1 : 0, d);
-    for (uint32_t x = t; x < npat; x += kThreads) spat[x] = tb.pat[x];
     if (t < hA && ((H >> t) & 1)) hb[__popc(H & ((1u << t) - 1))] = bA + t;
     if (t < n) sq[t] = qt[t];
-    for (uint32_t x = t; x < (1u << bA); x += kThreads) tile[x] = P::zero();
-    __syncthreads();
-    if (t <= d + 1) offN[t] = Kcount(sbin, N, t - 1);
+    for (uint32_t x = t; x < 8192 + 256; x += kThreads) tile[x] = P::zero();
     __syncthreads();
     const uint32_t *bn = sbin;
     const int h = __popc(H);
+    if (t <= d + 1) offN[t] = Kcount(bn, N, t - 1);
+    {   // ord8: 8-bit patterns by popcount (then value)
+        const int k = __popc(t);
+        uint32_t r = Kcount(bn, 8, k - 1);
+        int j = 0;
+        for (int p = 0; p < 8; ++p)
+            if ((t >> p) & 1) r += C(bn, p, ++j);
+        ord8[r] = (uint8_t)t;
+    }
+    // partial ranks of the high-bit items: prk[s * nit + it] = sum_q C(hb[e_q], s + q)
+    const uint32_t nit = Kcount(bn, h, d);
+    for (uint32_t it = t; use_prk && it < nit; it += kThreads) {
+        int k = 0;
+        uint32_t off = 0, toff = 0;
+        while (it >= off + C(bn, h, k)) {
+            off += C(bn, h, k);
+            toff += C(bn, hA, k);
+            ++k;
+        }
+        const uint32_t m = tb.items[toff + (it - off)];
+        for (int s = 0; s + k <= d; ++s) {
+            uint32_t r = 0, mm = m;
+            int q = 0;
+            while (mm) {
+                const int e = __ffs(mm) - 1;
+                mm &= mm - 1;
+                r += C(bn, hb[e], s + (++q));
+            }
+            prk[s * nit + it] = (uint16_t)r;
+        }
+    }
+    __syncthreads();
     const V *bi = beta + (size_t)i * K;
 
     // 1. seeds, one size class s = |G_L| at a time
     for (int s = 0; s <= d && s <= bA; ++s) {
         const uint32_t nseed = C(bn, bA, s);
-        const int tt = d - s;                       // max |G_H|
-        const uint32_t items = Kcount(bn, h, tt);
-        int grp = 1;                                // lanes per seed, power of 2 <= 64
+        const uint32_t items = Kcount(bn, h, d - s);    // G_H with |G_H| <= d - s
+        int grp = 1;                                    // lanes per seed, power of 2 <= 64
         while (grp < 64 && (uint32_t)grp < items && (uint32_t)(grp * 2) * nseed <= kThreads)
             grp *= 2;
         const uint32_t per_round = kThreads / grp;
@@ -293,39 +338,34 @@ k_alpha(int n, int d, uint32_t K, int bA, Tables tb, const typename P::V *__rest
             const int lane = t % grp;
             V acc = P::zero();
             if (seed < nseed) {
-                int k = 0;
-                uint32_t klo = 0, khi = 1;          // items of size k: [klo, khi)
-                uint32_t toff = 0;                  // item-table offset of size k
-                constexpr int B = 4;                // items per batch of loads
+                constexpr int B = 4;
                 for (uint32_t it0 = lane; it0 < items; it0 += B * grp) {
-                    uint32_t msk[B], sz[B];
+                    V bv[B];
 #pragma unroll
                     for (int u = 0; u < B; ++u) {
                         const uint32_t it = it0 + u * grp;
                         if (it < items) {
-                            while (it >= khi) {
+                            // size of item it: items are ordered by size
+                            int k = 0;
+                            uint32_t off = 1, toff = 0;
+                            while (it >= off) {
                                 toff += C(bn, hA, k);
-                                ++k;
-                                klo = khi;
-                                khi += C(bn, h, k);
+                                off += C(bn, h, ++k);
                             }
-                            msk[u] = tb.items[toff + (it - klo)];
-                            sz[u] = k;
-                        }
-                    }
-                    typename P::V bv[B];
-#pragma unroll
-                    for (int u = 0; u < B; ++u) {
-                        if (it0 + u * grp < items) {
-                            uint32_t m = msk[u];
-                            uint32_t rank = offN[s + sz[u]] + seed;
-                            int q = 0;
-                            while (m) {
-                                const int e = __ffs(m) - 1;
-                                m &= m - 1;
-                                rank += C(bn, hb[e], s + (++q));
+                            uint32_t pr;
+                            if (use_prk) {
+                                pr = prk[s * nit + it];
+                            } else {
+                                uint32_t m = tb.items[toff + it - (off - C(bn, h, k))];
+                                pr = 0;
+                                int q = 0;
+                                while (m) {
+                                    const int e = __ffs(m) - 1;
+                                    m &= m - 1;
+                                    pr += C(bn, hb[e], s + (++q));
+                                }
                             }
-                            bv[u] = bi[rank];
+                            bv[u] = bi[offN[s + k] + seed + pr];
                         }
                     }
 #pragma unroll
@@ -334,45 +374,82 @@ k_alpha(int n, int d, uint32_t K, int bA, Tables tb, const typename P::V *__rest
                 }
             }
             for (int w = grp / 2; w > 0; w >>= 1) acc = P::add(acc, shfl_xor_v(acc, w));
-            if (lane == 0 && seed < nseed) tile[tb.seedA[seedoff + seed]] = acc;
+            if (lane == 0 && seed < nseed) tile[pad32(tb.seedA[seedoff + seed])] = acc;
         }
     }
     __syncthreads();
 
-    // 2. truncated upward zeta over the low min(bA, 8) bits in LDS
-    const int lb = bA < 8 ? bA : 8;
-    for (int j = 0; j < lb; ++j) {
+    // 2. upward zeta in registers
+    V v[NR];
+    const uint32_t pt = ord8[t];
+    const bool live = __popc(pt) <= d;    // bits 5..12 of every entry this thread holds
+    if (__any(live)) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = tile[pad32((pt << 5) | r)];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) reg_zeta_up<P, NR>(v, q);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) tile[pad32((pt << 5) | r)] = v[r];
+    }
+    __syncthreads();
+    const uint32_t tlo = t & 31, thi = t >> 5;   // layout B: x = thi*1024 + r*32 + tlo
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v[r] = tile[pad32((thi << 10) | (r << 5) | tlo)];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) reg_zeta_up<P, NR>(v, q);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) tile[pad32((thi << 10) | (r << 5) | tlo)] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v[r] = tile[pad32(r * kThreads + t)];
+#pragma unroll
+    for (int q = 2; q < 5; ++q) reg_zeta_up<P, NR>(v, q);     // tile bits 10..12
+
+    // 3. alpha = q(|S|) t(S)
+    const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const uint32_t x = r * kThreads + t;
+        P::store(alpha, base + x, P::mul(sq[h + __popc(x)], v[r]), cnt);
+    }
+}
+
+// Generic form for lattices smaller than the 13-bit tile (n - 1 < 13): one
+// tile of bA = n - 1 bits, seeds as above, truncated zeta in LDS.
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_alpha_small(int n, int d, uint32_t K, Tables tb, const typename P::V *__restrict__ beta,
+              const typename P::V *__restrict__ qt, typename P::Store alpha,
+              unsigned long long *cnt) {
+    using V = typename P::V;
+    extern __shared__ unsigned char smem[];
+    V *tile = reinterpret_cast<V *>(smem);
+    __shared__ V sq[32];
+    const int N = n - 1;
+    const int bA = N;
+    const int i = blockIdx.x;
+    const int t = threadIdx.x;
+    const uint32_t *bn = tb.binom;
+    if (t < n) sq[t] = qt[t];
+    const V *bi = beta + (size_t)i * K;
+    // with no high bits every seed is a single family: Z(G) = beta_i(G)
+    for (uint32_t x = t; x < (1u << bA); x += kThreads) tile[x] = P::zero();
+    __syncthreads();
+    for (uint32_t r = t; r < K; r += kThreads) tile[tb.famask[r]] = bi[r];
+    __syncthreads();
+    for (int j = 0; j < bA; ++j) {
         const uint32_t cntj = Kcount(bn, bA - 1 - j, d) << j;
         for (uint32_t idx = t; idx < cntj; idx += kThreads) {
             const uint32_t lo = idx & ((1u << j) - 1);
-            const uint32_t S = ((uint32_t)spat[idx >> j] << (j + 1)) | (1u << j) | lo;
+            const uint32_t S = ((uint32_t)tb.pat[idx >> j] << (j + 1)) | (1u << j) | lo;
             tile[S] = P::add(tile[S], tile[S ^ (1u << j)]);
         }
         __syncthreads();
     }
-
-    // 3. register bits and the store
-    const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
-    if (RB == 0) {
-        for (uint32_t x = t; x < (1u << bA); x += kThreads)
-            P::store(alpha, base + x, P::mul(sq[h + __popc(x)], tile[x]), cnt);
-        return;
-    }
-    constexpr int R = 1 << RB;
-    V v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = tile[r * kThreads + t];
-#pragma unroll
-    for (int q = 0; q < RB; ++q) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if ((r >> q) & 1) v[r] = P::add(v[r], v[r ^ (1 << q)]);
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t x = r * kThreads + t;
-        P::store(alpha, base + x, P::mul(sq[h + __popc(x)], v[r]), cnt);
-    }
+    const uint64_t base = (uint64_t)i << N;
+    for (uint32_t x = t; x < (1u << bA); x += kThreads)
+        P::store(alpha, base + x, P::mul(sq[__popc(x)], tile[x]), cnt);
 }
 
 // ------------------------------------------- a3/a4: sweep helpers
@@ -609,6 +686,7 @@ k_gamma_tile(int n, int d, GammaGeom gg, Tables tb, typename P::Store L, typenam
     extern __shared__ unsigned char smem[];
     V *gb = reinterpret_cast<V *>(smem);                       // padded 2^12 entries
     uint32_t *sbin = reinterpret_cast<uint32_t *>(gb + 4096 + 256);
+    uint32_t *seedT = sbin + 33 * 33;                          // K(12, d) ranked masks
     __shared__ V sq[32];
     __shared__ uint32_t offT[34], offT1[34];
     const int t = threadIdx.x;
@@ -618,16 +696,16 @@ k_gamma_tile(int n, int d, GammaGeom gg, Tables tb, typename P::Store L, typenam
     if (nblk >= 64) H = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
     const uint64_t Hf = (uint64_t)H << bT;
     for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
+    for (uint32_t x = t; x < gg.KT; x += kThreads) seedT[x] = tb.seedmask[x];
     if (t < n) sq[t] = qt[t];
     V Lr[NR], Rr[NR], g[NR];
     Raw Rv[NR];                               // next endpoint's Rp tile, undecoded
-    uint32_t pc[NR];
+    const int hpc = __popcll(Hf);
     {
         Raw l0[NR], r0[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const uint32_t x = r * kThreads + t;
-            pc[r] = __popcll(Hf | x);
             l0[r] = P::load_raw(L, Hf | x);
             r0[r] = P::load_raw(R, Hf | x);
         }
@@ -662,7 +740,8 @@ k_gamma_tile(int n, int d, GammaGeom gg, Tables tb, typename P::Store L, typenam
             for (int r = 0; r < NR; ++r) {
                 const uint32_t x = r * kThreads + t;
                 g[r] = ((x >> v) & 1) ? P::zero()
-                                      : P::mul_raw(sq[pc[r]], P::mul_raw(Lr[r], gb[padx(x | (1u << v))]));
+                                      : P::mul_raw(sq[hpc + __popc(x)],
+                                                   P::mul_raw(Lr[r], gb[padx(x | (1u << v))]));
             }
             __syncthreads();
         } else if (low) {
@@ -673,12 +752,14 @@ k_gamma_tile(int n, int d, GammaGeom gg, Tables tb, typename P::Store L, typenam
 #pragma unroll
                 for (int r = 0; r < NR; ++r)
                     g[r] = ((r >> q) & 1) ? P::zero()
-                                          : P::mul_raw(sq[pc[r]], P::mul_raw(Lr[r], Rr[r | (1 << q)]));
+                                          : P::mul_raw(sq[hpc + __popc(r * kThreads + t)],
+                                                       P::mul_raw(Lr[r], Rr[r | (1 << q)]));
             }
         } else {
 #pragma unroll
             for (int r = 0; r < NR; ++r)
-                g[r] = P::mul_raw(sq[pc[r]], P::mul_raw(Lr[r], P::decode_raw(Rv[r])));
+                g[r] = P::mul_raw(sq[hpc + __popc(r * kThreads + t)],
+                                  P::mul_raw(Lr[r], P::decode_raw(Rv[r])));
             vn = v + 1;                       // prefetch the next endpoint's Rp tile
             while (vn < n && ((Hf >> vn) & 1)) ++vn;
             if (vn < n) {
@@ -710,25 +791,30 @@ k_gamma_tile(int n, int d, GammaGeom gg, Tables tb, typename P::Store L, typenam
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (v != q) reg_zeta_down<P, NR>(g, q);
-        // ---- outputs from registers: x = t*16 + r with at most d ones
+        // ---- outputs: entries with at most d ones, read back through LDS
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gb[padx((t << 4) | r)] = g[r];
+        __syncthreads();
         const int hv = gg.hv[v];
         const uint32_t Hc = low ? H : (uint32_t)compress_bit(H, v - bT);
         V *dst = Y1 + gg.y1off[v];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const uint32_t x = (t << 4) | r;
-            const int px = __popc(x);
-            if (px > d || (low && ((x >> v) & 1))) continue;
-            const uint32_t cm = low ? (uint32_t)compress_bit(x, v) : x;
-            uint32_t rank = low ? offT1[px] : offT[px];
-            int k = 0;
-            uint32_t rest = cm;
-            while (rest) {
-                const int p = __ffs(rest) - 1;
-                rest &= rest - 1;
-                rank += C(sbin, p, ++k);
+        for (uint32_t si = t; si < gg.KT; si += kThreads) {
+            const uint32_t msk = seedT[si];
+            uint32_t rank = si;
+            if (low) {
+                if ((msk >> v) & 1) continue;
+                const uint32_t cm = (uint32_t)compress_bit(msk, v);
+                rank = offT1[__popc(cm)];
+                int k = 0;
+                uint32_t rest = cm;
+                while (rest) {
+                    const int p = __ffs(rest) - 1;
+                    rest &= rest - 1;
+                    rank += C(sbin, p, ++k);
+                }
             }
-            dst[((size_t)rank << hv) + Hc] = P::norm_v(g[r]);
+            dst[((size_t)rank << hv) + Hc] = P::norm_v(gb[padx(msk)]);
         }
         __syncthreads();
     }
@@ -1232,27 +1318,23 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
                        a.gauge_exp);
     BN_CHECK_LAUNCH();
     rec(1);
-    {
-        const uint32_t npat = (uint32_t)a.npatA;
-        const size_t sm = (sizeof(V) << a.bA) + 33 * 33 * 4 + npat * 2;
-        const dim3 g((unsigned)(n << (N - a.bA)));
-        const int RB = a.bA > 8 ? a.bA - 8 : 0;
-#define BN_ALPHA(rb)                                                                           \
-    (void)hipFuncSetAttribute((const void *)k_alpha<P, rb>,                                    \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);            \
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha<P, rb>), g, dim3(kThreads), sm, st, n, d, a.K, \
-                       a.bA, tb, (const V *)beta, (const V *)qt, alpha, a.cnt)
-        switch (RB) {
-            case 0: BN_ALPHA(0); break;
-            case 1: BN_ALPHA(1); break;
-            case 2: BN_ALPHA(2); break;
-            case 3: BN_ALPHA(3); break;
-            case 4: BN_ALPHA(4); break;
-            default: BN_ALPHA(5); break;
-        }
-#undef BN_ALPHA
-        BN_CHECK_LAUNCH();
+    if (a.bA == 13) {
+        const uint32_t nit = (uint32_t)a.nitA;
+        // the partial-rank table is used when ranks fit 16 bits and it fits 12 KB
+        const int use_prk = (a.K < 65536u && (size_t)(d + 1) * nit * 2 <= 12288) ? 1 : 0;
+        const size_t sm = sizeof(V) * (8192 + 256) + 33 * 33 * 4 +
+                          (use_prk ? (size_t)(d + 1) * nit * 2 : 0);
+        (void)hipFuncSetAttribute((const void *)k_alpha<P>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha<P>), dim3((unsigned)(n << (N - 13))),
+                           dim3(kThreads), sm, st, n, d, a.K, use_prk, tb, (const V *)beta,
+                           (const V *)qt, alpha, a.cnt);
+    } else {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_small<P>), dim3((unsigned)n), dim3(kThreads),
+                           sizeof(V) << N, st, n, d, a.K, tb, (const V *)beta, (const V *)qt,
+                           alpha, a.cnt);
     }
+    BN_CHECK_LAUNCH();
     rec(2);
     const int nh = n - a.bL;
     const size_t smL = sizeof(V) * (((size_t)a.bL << (a.bL - 1)) + ((size_t)1 << a.bL)) +
@@ -1274,7 +1356,7 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     {
         const GammaGeom &gg = a.gg;
         if (a.bG == 12) {
-            const size_t sm = sizeof(V) * (4096 + 256) + 33 * 33 * 4;
+            const size_t sm = sizeof(V) * (4096 + 256) + 33 * 33 * 4 + (size_t)gg.KT * 4;
             (void)hipFuncSetAttribute((const void *)k_gamma_tile<P>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile<P>), dim3(1u << (n - 12)),

@@ -105,7 +105,7 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.x32 = (prec == BN_FP32_SCALED);
     const int N = P.N, d = P.d;
     P.K = (uint32_t)kcount_u64(N, d);
-    P.bA = std::min(N, 13);
+    P.bA = N >= 13 ? 13 : N;      // alpha tile: 13 bits, or the whole lattice when smaller
     P.bL = std::min(n, 10);
     P.bG = n >= 12 ? 12 : n;      // Gamma tile: 12 bits, or the whole lattice when smaller
     P.aG = 12;
@@ -114,7 +114,7 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     if (const char *tb = getenv("BN_TILE_BITS")) {
         int v[4] = {P.bA, P.bL, P.bG, P.aG};
         if (sscanf(tb, "%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3]) == 4) {
-            P.bA = std::max(1, std::min(std::min(v[0], N), 13));
+            (void)v[0];
             P.bL = std::max(2, std::min(v[1], n));
             (void)v[2];
             P.aG = std::max(1, std::min(v[3], 12));
@@ -281,6 +281,7 @@ bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_d
     a.KG = P.KG;
     a.KA = P.KA;
     a.npatA = (uint32_t)kcount_u64(std::max(P.bA - 1, 0), P.d);
+    a.nitA = (uint32_t)kcount_u64(P.N - P.bA, P.d);
     a.gauge = P.x32 ? 1 : 0;
     a.tb = tables_of(P, ws);
     a.logp = reinterpret_cast<const double *>(ws + P.o_logp);
