@@ -679,7 +679,8 @@ __device__ inline uint32_t padx(uint32_t x) { return x + (x >> 4); }
 template <class P>
 __global__ void __launch_bounds__(kThreads)
 k_gamma_tile(int n, int d, GammaGeom gg, Tables tb, typename P::Store L, typename P::Store R,
-             const typename P::V *__restrict__ qt, typename P::V *__restrict__ Y1) {
+             const typename P::V *__restrict__ qt, typename P::V *__restrict__ Y1,
+             typename P::V *__restrict__ part) {
     using V = typename P::V;
     using Raw = typename P::Raw;
     constexpr int bT = 12, NR = 16;
@@ -720,6 +721,33 @@ k_gamma_tile(int n, int d, GammaGeom gg, Tables tb, typename P::Store L, typenam
     if (vn < n) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) Rv[r] = P::load_raw(R, Hf | (r * kThreads + t) | (1ull << vn));
+    }
+    {   // invariant partials: sum of L(S) Rp(S) over the tile, per |x| (x = r*256 + t)
+        V lr[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) lr[k] = P::zero();
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const V prod = P::mul(Lr[r], Rr[r]);
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+                if (__popc(r) == k) lr[k] = P::add(lr[k], prod);
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) gb[t * 5 + k] = lr[k];
+        __syncthreads();
+        {   // layer l = t / 16 of the tile: 16 lanes x 16 slots, then a lane tree
+            const int l = t >> 4, j = t & 15;
+            V acc = P::zero();
+            if (l <= bT) {
+                for (int u = j; u < kThreads; u += 16) {
+                    const int k = l - __popc(u);
+                    if (k >= 0 && k <= 4) acc = P::add(acc, gb[u * 5 + k]);
+                }
+            }
+            for (int w = 8; w > 0; w >>= 1) acc = P::add(acc, shfl_xor_v(acc, w));
+            if (l <= bT && j == 0) part[(size_t)H * (bT + 1) + l] = acc;
+        }
     }
     __syncthreads();
     if (t <= d + 1) {
@@ -1360,7 +1388,7 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
             (void)hipFuncSetAttribute((const void *)k_gamma_tile<P>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile<P>), dim3(1u << (n - 12)),
-                               dim3(kThreads), sm, st, n, d, gg, tb, L, R, (const V *)qt, Y1);
+                               dim3(kThreads), sm, st, n, d, gg, tb, L, R, (const V *)qt, Y1, part);
         } else {
             const int bT = a.bG;
             const size_t sm = sizeof(V) * ((size_t)1 << bT) + 33 * 33 * 4 + (size_t)gg.KT * 4 +
@@ -1400,9 +1428,16 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
                        (const uint32_t *)tb.famask, (const V *)beta, (const V *)gam, L, a.post,
                        a.resid);
     BN_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_inv1<P>, dim3(1u << nh), dim3(kThreads), 0, st, n, a.bL, tb, L, R, part);
-    BN_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_inv2<P>, dim3(n + 1), dim3(kThreads), 0, st, n, a.bL, (const V *)part,
+    // layer sums of L(S) Rp(S): partials per tile come from the Gamma tile
+    // kernel (12-bit tiles) or from k_inv1 (sweep tiles, small lattices)
+    int bI = 12;
+    if (a.bG != 12) {
+        bI = a.bL;
+        hipLaunchKernelGGL(k_inv1<P>, dim3(1u << nh), dim3(kThreads), 0, st, n, a.bL, tb, L, R,
+                           part);
+        BN_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL(k_inv2<P>, dim3(n + 1), dim3(kThreads), 0, st, n, bI, (const V *)part,
                        layer);
     BN_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_finalize<P>, dim3(1), dim3(64), 0, st, n, L, R, (const V *)layer,

@@ -198,7 +198,8 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.o_Y1 = take((size_t)P.y1_elems * V);
     if (P.two_level) P.o_Y2 = take((size_t)P.y2_elems * V);
     P.o_gam = take((size_t)n * P.K * V);
-    P.o_part = take(((size_t)1 << nh) * (P.bL + 1) * V);
+    P.o_part = take(std::max(((size_t)1 << nh) * (P.bL + 1),
+                             n >= 12 ? ((size_t)1 << (n - 12)) * 13 : (size_t)0) * V);
     if (with_post) P.o_post = take((size_t)n * n * 8);
     if (with_data) P.o_data = take((size_t)n * (size_t)std::max(m, 1));
     P.total = o;
