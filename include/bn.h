@@ -91,6 +91,8 @@ typedef struct {
     uint64_t flushed;              /* FP32-scaled: nonzero entries rounded to 0 below
                                       the bottom of the exponent range               */
     double ms_scores, ms_alpha, ms_fwd, ms_bwd, ms_gamma, ms_edges, ms_total;
+    double ms_queue;               /* serving: submit -> admission (host clock)      */
+    double ms_latency;             /* serving: submit -> completion observed          */
 } bn_report;
 
 /* Number of parent sets of one node: K(n-1, d) = sum_{k<=min(d,n-1)} C(n-1, k).

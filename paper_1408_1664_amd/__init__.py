@@ -51,7 +51,8 @@ class Report(ctypes.Structure):
                 ("ms_scores", ctypes.c_double), ("ms_alpha", ctypes.c_double),
                 ("ms_fwd", ctypes.c_double), ("ms_bwd", ctypes.c_double),
                 ("ms_gamma", ctypes.c_double), ("ms_edges", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("ms_queue", ctypes.c_double),
+                ("ms_latency", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
