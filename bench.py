@@ -92,6 +92,69 @@ def roofline(res):
     return out
 
 
+def serving(bn, datagen, num=512, check=8):
+    """Serving stream: 512 requests, n ~ U{10..22}, m ~ U{100..2000}, arity
+    in {2,3}, d = 3, FP32-scaled. Closed-loop saturation first (all requests
+    at t = 0), then open-loop Poisson arrivals at 0.5 and 0.8 of that rate;
+    latency = arrival (submit) -> completion observed by the server."""
+    import threading
+
+    import numpy as np
+
+    reqs = datagen.serving_stream(num, seed=4)
+    data = [datagen.request_dataset(r) for r in reqs]
+
+    def run(arrivals):
+        srv = bn.Server(mem_budget_bytes=0, max_active=16)
+        tickets = [None] * num
+        t0 = time.perf_counter()
+
+        def submitter():
+            for j, (ds, r) in enumerate(zip(data, reqs)):
+                if arrivals is not None:
+                    delay = t0 + arrivals[j] - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                tickets[j] = srv.submit(ds.data, ds.arity, r["d"], precision="fp32",
+                                        ess=r["ess"])
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat, posts = [], []
+        for j in range(num):
+            while tickets[j] is None:
+                time.sleep(1e-4)
+            s, post, rep = srv.poll(tickets[j], timeout_us=-1)
+            assert s == bn.BN_OK, s
+            lat.append(rep["ms_latency"])
+            if j < check:
+                posts.append(post)
+        th.join()
+        wall = time.perf_counter() - t0
+        srv.close()
+        lat = np.array(lat)
+        return dict(seconds=wall, solves_per_s=num / wall, p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99))), posts
+
+    sat, posts = run(None)
+    same = True
+    for j in range(check):
+        alone, _ = bn.edge_posteriors(data[j].data, data[j].arity, reqs[j]["d"], precision="fp32",
+                                      ess=reqs[j]["ess"])
+        same = same and bool(np.array_equal(alone, posts[j]))
+    rng = np.random.default_rng(4)
+    out = dict(requests=num, workload="512 requests, n~U{10..22}, m~U{100..2000}, arity~U{2,3}, "
+                                       "d=3, FP32-scaled",
+               closed_loop=sat, open_loop=[], served_equals_alone=same, checked=check)
+    for frac in (0.5, 0.8):
+        rate = frac * sat["solves_per_s"]
+        gaps = rng.exponential(1.0 / rate, size=num)
+        res, _ = run(np.cumsum(gaps))
+        res["offered_rate"] = rate
+        out["open_loop"].append(res)
+    return out
+
+
 def cpu_baseline(datagen, name, sample_n):
     from oracle import oracle as O
     ds, p = datagen.workload(name)
@@ -116,6 +179,7 @@ def main():
                     help="extra lines prec@workload:steps, comma separated ('' for none)")
     ap.add_argument("--cpu-sample-n", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solve is single-GPU (multi-GPU sharding of "
@@ -146,6 +210,12 @@ def main():
         comps.append(line)
         print(f"# {wl} {prec}: {r['ms_per_step']:.2f} ms/step, {r['cells_per_s']:.3e} cells/s",
               file=sys.stderr, flush=True)
+    serve = None
+    if not args.no_serving:
+        serve = serving(bn, datagen)
+        print(f"# serving: {serve['closed_loop']['solves_per_s']:.0f} solves/s saturated, "
+              f"open-loop p50/p99 {[(round(o['p50_ms'], 2), round(o['p99_ms'], 2)) for o in serve['open_loop']]}",
+              file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(datagen, args.workload, args.cpu_sample_n)
@@ -175,6 +245,7 @@ def main():
         "saturated": head["saturated"],
         "flushed": head["flushed"],
         "comparisons": comps,
+        "serving": serve,
     }
     print(json.dumps(out), flush=True)
 
