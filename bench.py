@@ -27,18 +27,23 @@ HBM_PEAK_GBS = 8000.0
 STORE_BYTES = {"fp32": 5, "fp64": 8}
 
 
-def phase_bytes(phase, n, prec):
-    """Algorithmic HBM bytes of one solve's phase: every value read or written
-    once (values: E bytes; alpha n 2^(n-1) entries, L and Rp 2^n each)."""
+# Kernels timed alone by the phase timer (one launch each per solve) and the
+# timer entry that brackets each.
+SINGLE_LAUNCH = {"alpha": "k_alpha", "gamma_tile": "k_gamma_tile"}
+
+
+def kernel_bytes(phase, n, prec):
+    """Algorithmic HBM bytes of one launch, E bytes per stored value:
+    alpha writes n 2^(n-1) entries; the Gamma in-tile kernel consumes, for
+    every endpoint v and every S not containing v, L(S) and Rp(S+v): 2E per
+    (v, S) pair, n 2^(n-1) pairs."""
     E = STORE_BYTES[prec]
     A = n * 2 ** (n - 1)
     if phase == "alpha":
-        return E * A                       # alpha written once
-    if phase in ("forward", "backward"):
-        return E * A + E * 2 ** n          # alpha read once, L (Rp) written once
-    if phase == "gamma":
-        return 2 * E * A                   # L(S) and Rp(S+v) read for every (S, v not in S)
-    return None
+        return E * A
+    if phase == "gamma_tile":
+        return 2 * E * A
+    raise ValueError(phase)
 
 
 def measure(bn, torch, datagen, name, prec, steps, warmup):
@@ -78,18 +83,27 @@ def measure(bn, torch, datagen, name, prec, steps, warmup):
 
 
 def roofline(res):
-    n, prec = res["n"], res["precision"]
-    ph = {k: v for k, v in res["phases_ms"].items() if k != "total"}
-    dom = max(ph, key=ph.get)
-    b = phase_bytes(dom, n, prec)
-    out = dict(kernel=dom, ms=ph[dom])
-    if b is None:
-        out.update(bound="alu", achieved=None, peak=None, unit=None, frac=None, traffic=None)
-        return out
+    """HBM roofline of the dominant single-launch kernel: algorithmic bytes of
+    its launch over its HIP-event duration (averaged over the timed steps)."""
+    n, prec, ph = res["n"], res["precision"], res["phases_ms"]
+    dom = max(SINGLE_LAUNCH, key=lambda k: ph[k])
+    b = kernel_bytes(dom, n, prec)
     ach = b / (ph[dom] * 1e-3) / 1e9
-    out.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-               frac=ach / HBM_PEAK_GBS, traffic=None, algorithmic_bytes=b)
-    return out
+    return dict(kernel=SINGLE_LAUNCH[dom], ms=ph[dom], bound="hbm", achieved=ach,
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None,
+                algorithmic_bytes=b)
+
+
+def copy_calibration(nbytes):
+    """One device-to-device copy of nbytes (torch's copy kernel): the known
+    traffic that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
 
 
 def serving(bn, datagen, num=512, check=8):
@@ -180,11 +194,17 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solve is single-GPU (multi-GPU sharding of "
               "the lattice is a design, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import numpy as np
     import torch
@@ -238,6 +258,7 @@ def main():
                    "score": "BDeu(ess=1)", "prior": "q=1, rho_k=1/C(n-1,k)"},
         "roofline": {k: rf[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_kernel": rf["kernel"],
+        "roofline_kernel_ms": rf["ms"],
         "cpu_baseline": cpu,
         "phases_ms": head["phases_ms"],
         "log_LV": head["log_LV"],

@@ -160,18 +160,20 @@ bn_status bn_edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *d
  * does not synchronise). Create it on the device that runs the solves.
  * bn_timer_read, valid once that stream has been synchronised, returns the
  * milliseconds of the last solve that used the timer:
- *   ms[0] parameters, tables, local scores and prior/gauges (a1)
- *   ms[1] alpha, truncated upward zeta (a2)
- *   ms[2] forward sweep, all layers (a3)
- *   ms[3] backward sweep, all layers (a4)
- *   ms[4] Gamma: product and truncated downward zeta (a5, a6)
- *   ms[5] edge sums, invariants and diagnostics (a7)
+ *   ms[0] parameters, tables, local scores and prior/gauges (Eq. 6)
+ *   ms[1] alpha, truncated upward zeta (Eq. 7, Alg. 2): one kernel launch
+ *   ms[2] forward sweep, all layers (Eq. 9)
+ *   ms[3] backward sweep, all layers (Eq. 10)
+ *   ms[4] Gamma: product and truncated downward zeta (Eq. 12, Alg. 3)
+ *   ms[5] edge sums, invariants and diagnostics (Eq. 11)
  *   ms[6] total
+ *   ms[7] the Gamma in-tile kernel alone (one launch; part of ms[4]): the
+ *         products and the zeta over the low tile bits
  */
 typedef struct bn_timer bn_timer;
 bn_status bn_timer_create(bn_timer **timer);
 bn_status bn_timer_destroy(bn_timer *timer);
-bn_status bn_timer_read(const bn_timer *timer, double ms[7]);
+bn_status bn_timer_read(const bn_timer *timer, double ms[8]);
 
 /*
  * Serving: a server thread batches solves of mixed n, m and arity as they

@@ -1409,6 +1409,7 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
 #undef BN_GTILE
         }
         BN_CHECK_LAUNCH();
+        rec(7);
         if (gg.blk1[n] > 0) {
             hipLaunchKernelGGL(k_gamma_high1<P>, dim3(gg.blk1[n]), dim3(kThreads),
                                sizeof(V) << gg.hmax1, st, n, d, a.K, gg, tb, (const V *)Y1, gam);

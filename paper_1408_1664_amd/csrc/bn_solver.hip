@@ -460,26 +460,25 @@ bn_status bn_edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *d
 bn_status bn_timer_create(bn_timer **timer) {
     if (!timer) return BN_EINVAL;
     bn_timer *t = new bn_timer();
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < 8; ++k) {
         if (hipEventCreate(&t->ev.ev[k]) != hipSuccess) {
             for (int j = 0; j < k; ++j) (void)hipEventDestroy(t->ev.ev[j]);
             delete t;
             return BN_EDEVICE;
         }
     }
-    t->ev.ev[7] = nullptr;
     *timer = t;
     return BN_OK;
 }
 
 bn_status bn_timer_destroy(bn_timer *timer) {
     if (!timer) return BN_EINVAL;
-    for (int k = 0; k < 7; ++k) (void)hipEventDestroy(timer->ev.ev[k]);
+    for (int k = 0; k < 8; ++k) (void)hipEventDestroy(timer->ev.ev[k]);
     delete timer;
     return BN_OK;
 }
 
-bn_status bn_timer_read(const bn_timer *timer, double ms[7]) {
+bn_status bn_timer_read(const bn_timer *timer, double ms[8]) {
     if (!timer || !ms) return BN_EINVAL;
     for (int k = 1; k < 7; ++k) {
         float x = 0;
@@ -491,6 +490,10 @@ bn_status bn_timer_read(const bn_timer *timer, double ms[7]) {
     if (hipEventElapsedTime(&tot, timer->ev.ev[0], timer->ev.ev[6]) != hipSuccess)
         return BN_EDEVICE;
     ms[6] = tot;
+    float gt = 0;
+    if (hipEventElapsedTime(&gt, timer->ev.ev[4], timer->ev.ev[7]) != hipSuccess)
+        return BN_EDEVICE;
+    ms[7] = gt;
     return BN_OK;
 }
 
