@@ -93,6 +93,9 @@ typedef struct {
     double ms_scores, ms_alpha, ms_fwd, ms_bwd, ms_gamma, ms_edges, ms_total;
     double ms_queue;               /* serving: submit -> admission (host clock)      */
     double ms_latency;             /* serving: submit -> completion observed          */
+    uint64_t fallback_tiles;       /* zeta tiles (alpha, Gamma) whose range did not fit
+                                      one FP64 scale and were recomputed in the solve's
+                                      own number system                              */
 } bn_report;
 
 /* Number of parent sets of one node: K(n-1, d) = sum_{k<=min(d,n-1)} C(n-1, k).
@@ -143,7 +146,7 @@ struct bn_timer;
  *   dev_diag:        DEVICE or NULL; 8 doubles: [0] log F(V), [1] max invariant
  *                    residual, [2] saturated count, [3] flushed count,
  *                    [4] |log Rp(empty) - log F(V)|, [5] max layer-sum residual,
- *                    [6] max edge-sum residual.
+ *                    [6] max edge-sum residual, [7] fallback tiles (bn_report).
  *   timer:           NULL, or a bn_timer to receive per-phase HIP events.
  * Enqueues the work and returns without waiting; the results are valid after
  * the stream is synchronised. Data values are not range-checked on the host
@@ -168,7 +171,8 @@ bn_status bn_edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *d
  *   ms[5] edge sums, invariants and diagnostics (Eq. 11)
  *   ms[6] total
  *   ms[7] the Gamma in-tile kernel alone (one launch; part of ms[4]): the
- *         products and the zeta over the low tile bits
+ *         products and the zeta over the low tile bits (the recomputation of
+ *         fallback tiles, if any, is not included)
  */
 typedef struct bn_timer bn_timer;
 bn_status bn_timer_create(bn_timer **timer);

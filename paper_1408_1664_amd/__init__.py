@@ -52,7 +52,7 @@ class Report(ctypes.Structure):
                 ("ms_fwd", ctypes.c_double), ("ms_bwd", ctypes.c_double),
                 ("ms_gamma", ctypes.c_double), ("ms_edges", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("ms_queue", ctypes.c_double),
-                ("ms_latency", ctypes.c_double)]
+                ("ms_latency", ctypes.c_double), ("fallback_tiles", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

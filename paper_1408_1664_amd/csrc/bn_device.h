@@ -79,6 +79,30 @@ struct PolLog {
         *reinterpret_cast<double2 *>(s.p + i) = make_double2(v[0], v[1]);
         *reinterpret_cast<double2 *>(s.p + i + 2) = make_double2(v[2], v[3]);
     }
+    // Linear tiles: a value x is held as the plain double x * 2^-T (T a
+    // natural-log offset here) so that a zeta over the tile costs one FP64
+    // add per step. anchor_of places the reference value a at 2^-1000,
+    // leaving about 2,000 binary orders of headroom above it.
+    using Anchor = double;
+    __device__ static inline bool anchor_of(V a, Anchor *T) {
+        if (!(a > -1e300)) return false;
+        *T = a + 1000.0 * 0.69314718055994530942;
+        return true;
+    }
+    __device__ static inline double to_lin(V x, Anchor T) {
+        return x > -1e300 ? exp(x - T) : 0.0;
+    }
+    __device__ static inline double prod_lin(V a, V b, V c, Anchor T) {
+        const double s = a + b + c;
+        return s > -1e300 ? exp(s - T) : 0.0;
+    }
+    __device__ static inline V from_lin(double y, Anchor T) {
+        return y > 0.0 ? log(y) + T : zero();
+    }
+    // from_lin(y) * q
+    __device__ static inline V from_lin_q(double y, V q, Anchor T) {
+        return q > -1e300 ? from_lin(y, T) + q : zero();
+    }
 };
 
 // ------------------------------------------------------- FP32 + exponent
@@ -206,6 +230,35 @@ struct PolX32 {
         for (int k = 0; k < 4; ++k) b |= encode(v[k], &f[k], cnt) << (8 * k);
         *reinterpret_cast<float4 *>(s.f + i) = make_float4(f[0], f[1], f[2], f[3]);
         *reinterpret_cast<uint32_t *>(s.b + i) = b;
+    }
+    // Linear tiles: a value x is held as the plain double x * 2^-T, T a
+    // multiple of 64, so that a zeta over the tile costs one FP64 add per
+    // step. anchor_of places the reference value a within 2^-1032 .. 2^-968,
+    // leaving at least 1,990 binary orders of headroom above it; values far
+    // below the reference fall into the subnormal range or to zero.
+    using Anchor = int;
+    __device__ static inline bool anchor_of(V a, Anchor *T) {
+        if (!(a.f > 0.0f)) return false;
+        const int e = a.e + ((__float_as_int(a.f) >> 23) & 0xff) - 127;  // floor(log2 a)
+        *T = ((e + 1032) >> 6) << 6;
+        return true;
+    }
+    __device__ static inline double to_lin(V x, Anchor T) {
+        return ldexp((double)x.f, max(x.e - T, -2000));
+    }
+    __device__ static inline double prod_lin(V a, V b, V c, Anchor T) {
+        return ldexp((double)(a.f * b.f * c.f), max(a.e + b.e + c.e - T, -2000));
+    }
+    // Back to a normalised X32 (f in [2^-32, 2^32]); y >= 0 and finite.
+    __device__ static inline V from_lin(double y, Anchor T) {
+        if (!(y > 0.0)) return zero();
+        const int e = __builtin_amdgcn_frexp_exp(y);     // y in [2^(e-1), 2^e)
+        const int k = ((e + 31) >> 6) << 6;
+        return X32{(float)ldexp(y, -k), T + k};
+    }
+    // from_lin(y) * q
+    __device__ static inline V from_lin_q(double y, V q, Anchor T) {
+        return from_lin(y * (double)q.f, T + q.e);
     }
 };
 

@@ -9,6 +9,8 @@
 //
 // Tiling: a tile is 2^b consecutive masks (the low b bits vary inside a
 // workgroup, the high bits select the tile). Every kernel runs 256 threads.
+#include <algorithm>
+
 #include "bn_device.h"
 #include "bn_kernels.h"
 
@@ -199,10 +201,14 @@ __global__ void k_prep(int n, int d, uint32_t K, const uint32_t *binom,
                        const double *__restrict__ logp, const double *__restrict__ log_rho,
                        const double *__restrict__ log_q, int gauge,
                        typename P::V *__restrict__ beta, typename P::V *__restrict__ qt,
-                       double *__restrict__ gauge_exp) {
+                       double *__restrict__ gauge_exp, uint32_t *fbA, uint32_t *fbG) {
     __shared__ double red[kThreads];
     const int i = blockIdx.x;
     const int t = threadIdx.x;
+    if (i == 0 && t == 0) {
+        if (fbA) fbA[0] = 0;
+        if (fbG) fbG[0] = 0;
+    }
     const int N = n - 1;
     double mx = -__builtin_huge_val();
     for (uint32_t r = t; r < K; r += kThreads) {
@@ -264,10 +270,11 @@ __device__ inline void reg_zeta_up(typename P::V *v, int q) {
 //     and bits 10..12 (x = r*256 + t), with two LDS transposes.
 //  3. alpha = q(|S|) * t(S), stored coalesced from the last layout.
 template <class P>
-__global__ void __launch_bounds__(kThreads)
-k_alpha(int n, int d, uint32_t K, int use_prk, Tables tb, const typename P::V *__restrict__ beta,
-        const typename P::V *__restrict__ qt, typename P::Store alpha,
-        unsigned long long *cnt) {
+__device__ __forceinline__ void alpha_tile(int n, int d, uint32_t K, int use_prk, const Tables &tb,
+                                           const typename P::V *__restrict__ beta,
+                                           const typename P::V *__restrict__ qt,
+                                           const typename P::Store &alpha,
+                                           unsigned long long *cnt, uint32_t blk) {
     using V = typename P::V;
     constexpr int bA = 13, NR = 32;
     extern __shared__ unsigned char smem[];
@@ -280,8 +287,8 @@ k_alpha(int n, int d, uint32_t K, int use_prk, Tables tb, const typename P::V *_
     __shared__ uint8_t ord8[256];
     const int N = n - 1;
     const int hA = N - bA;
-    const int i = blockIdx.x >> hA;
-    const uint32_t H = blockIdx.x & ((1u << hA) - 1);
+    const int i = blk >> hA;
+    const uint32_t H = blk & ((1u << hA) - 1);
     const int t = threadIdx.x;
     for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
     if (t < hA && ((H >> t) & 1)) hb[__popc(H & ((1u << t) - 1))] = bA + t;
@@ -412,6 +419,235 @@ k_alpha(int n, int d, uint32_t K, int use_prk, Tables tb, const typename P::V *_
     for (int r = 0; r < NR; ++r) {
         const uint32_t x = r * kThreads + t;
         P::store(alpha, base + x, P::mul(sq[h + __popc(x)], v[r]), cnt);
+    }
+}
+
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_alpha(int n, int d, uint32_t K, int use_prk, Tables tb, const typename P::V *__restrict__ beta,
+        const typename P::V *__restrict__ qt, typename P::Store alpha,
+        unsigned long long *cnt) {
+    alpha_tile<P>(n, d, K, use_prk, tb, beta, qt, alpha, cnt, blockIdx.x);
+}
+
+// Recomputation of the tiles listed by k_alpha_lin (list[0] entries,
+// list[1 + j] = i * 2^(N-13) + H): the grid walks the list.
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_alpha_fb(int n, int d, uint32_t K, int use_prk, Tables tb,
+           const typename P::V *__restrict__ beta, const typename P::V *__restrict__ qt,
+           typename P::Store alpha, unsigned long long *cnt, const uint32_t *list) {
+    const uint32_t ntile = list[0];
+    for (uint32_t it = blockIdx.x; it < ntile; it += gridDim.x) {
+        __syncthreads();
+        alpha_tile<P>(n, d, K, use_prk, tb, beta, qt, alpha, cnt, list[1 + it]);
+    }
+}
+
+// A double held in LDS as two 32-bit words (4-byte alignment): it moves with
+// 32-bit LDS instructions. The alpha tile's transposes run at about twice
+// the speed this way than with 64-bit LDS instructions.
+struct W2 {
+    uint32_t lo, hi;
+};
+__device__ inline W2 w2_of(double x) {
+    W2 w;
+    __builtin_memcpy(&w, &x, 8);
+    return w;
+}
+__device__ inline double dbl_of(W2 w) {
+    double x;
+    __builtin_memcpy(&x, &w, 8);
+    return x;
+}
+
+__device__ inline void fb_push(uint32_t *fb, uint32_t id) {
+    const uint32_t k = atomicAdd(fb, 1u);
+    fb[1 + k] = id;
+}
+
+template <int NR>
+__device__ inline void lin_zeta_up(double *v, int q) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if ((r >> q) & 1) v[r] += v[r ^ (1 << q)];
+}
+
+// Linear-tile form of k_alpha (same workgroup geometry, seeds and layouts).
+// Every entry of the tile, alpha_i(H + x) / q, is a sum of seeds that
+// includes Z(empty), so the tile is scaled by one power of two (a log offset
+// for the log-space system) that puts Z(empty) near 2^-1000 and the upward
+// zeta runs on plain doubles: one FP64 add per step instead of an aligned
+// add. Entries far below Z(empty) may lose bits to the subnormal range;
+// that changes no output by more than 2^-60 of itself. If the largest entry
+// (x = all ones, the sum of every seed) overflows the double range, or
+// Z(empty) is zero, the tile stores nothing and goes to the fallback list
+// for k_alpha_fb. force_fb sends every tile there (tests).
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_alpha_lin(int n, int d, uint32_t K, int use_prk, int force_fb, Tables tb,
+            const typename P::V *__restrict__ beta, const typename P::V *__restrict__ qt,
+            typename P::Store alpha, unsigned long long *cnt, uint32_t *fb) {
+    using V = typename P::V;
+    using A = typename P::Anchor;
+    constexpr int bA = 13, NR = 32;
+    extern __shared__ unsigned char smem[];
+    W2 *tile = reinterpret_cast<W2 *>(smem);                       // pad32(2^13)
+    uint32_t *sbin = reinterpret_cast<uint32_t *>(tile + 8192 + 256);
+    uint16_t *prk = reinterpret_cast<uint16_t *>(sbin + 33 * 33);  // (d+1) x items
+    __shared__ int hb[32];
+    __shared__ uint32_t offN[34];
+    __shared__ V sq[32];
+    __shared__ uint8_t ord8[256];
+    __shared__ V sz0;
+    __shared__ int sfail;
+    const int N = n - 1;
+    const int hA = N - bA;
+    const int i = blockIdx.x >> hA;
+    const uint32_t H = blockIdx.x & ((1u << hA) - 1);
+    const int t = threadIdx.x;
+    for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
+    if (t < hA && ((H >> t) & 1)) hb[__popc(H & ((1u << t) - 1))] = bA + t;
+    if (t < n) sq[t] = qt[t];
+    for (uint32_t x = t; x < 8192 + 256; x += kThreads) tile[x] = w2_of(0.0);
+    __syncthreads();
+    const uint32_t *bn = sbin;
+    const int h = __popc(H);
+    if (t <= d + 1) offN[t] = Kcount(bn, N, t - 1);
+    {   // ord8: 8-bit patterns by popcount (then value)
+        const int k = __popc(t);
+        uint32_t r = Kcount(bn, 8, k - 1);
+        int j = 0;
+        for (int p = 0; p < 8; ++p)
+            if ((t >> p) & 1) r += C(bn, p, ++j);
+        ord8[r] = (uint8_t)t;
+    }
+    const uint32_t nit = Kcount(bn, h, d);
+    for (uint32_t it = t; use_prk && it < nit; it += kThreads) {
+        int k = 0;
+        uint32_t off = 0, toff = 0;
+        while (it >= off + C(bn, h, k)) {
+            off += C(bn, h, k);
+            toff += C(bn, hA, k);
+            ++k;
+        }
+        const uint32_t m = tb.items[toff + (it - off)];
+        for (int s = 0; s + k <= d; ++s) {
+            uint32_t r = 0, mm = m;
+            int q = 0;
+            while (mm) {
+                const int e = __ffs(mm) - 1;
+                mm &= mm - 1;
+                r += C(bn, hb[e], s + (++q));
+            }
+            prk[s * nit + it] = (uint16_t)r;
+        }
+    }
+    __syncthreads();
+    const V *bi = beta + (size_t)i * K;
+
+    // 1. seeds as in k_alpha; Z(empty) first, which fixes the scale
+    A T{};
+    bool ok = true;
+    for (int s = 0; s <= d && s <= bA; ++s) {
+        const uint32_t nseed = C(bn, bA, s);
+        const uint32_t items = Kcount(bn, h, d - s);
+        int grp = 1;
+        while (grp < 64 && (uint32_t)grp < items && (uint32_t)(grp * 2) * nseed <= kThreads)
+            grp *= 2;
+        const uint32_t per_round = kThreads / grp;
+        const uint32_t seedoff = Kcount(bn, bA, s - 1);
+        for (uint32_t base = 0; base < nseed; base += per_round) {
+            const uint32_t seed = base + t / grp;
+            const int lane = t % grp;
+            V acc = P::zero();
+            if (seed < nseed) {
+                constexpr int B = 4;
+                for (uint32_t it0 = lane; it0 < items; it0 += B * grp) {
+                    V bv[B];
+#pragma unroll
+                    for (int u = 0; u < B; ++u) {
+                        const uint32_t it = it0 + u * grp;
+                        if (it < items) {
+                            int k = 0;
+                            uint32_t off = 1, toff = 0;
+                            while (it >= off) {
+                                toff += C(bn, hA, k);
+                                off += C(bn, h, ++k);
+                            }
+                            uint32_t pr;
+                            if (use_prk) {
+                                pr = prk[s * nit + it];
+                            } else {
+                                uint32_t m = tb.items[toff + it - (off - C(bn, h, k))];
+                                pr = 0;
+                                int q = 0;
+                                while (m) {
+                                    const int e = __ffs(m) - 1;
+                                    m &= m - 1;
+                                    pr += C(bn, hb[e], s + (++q));
+                                }
+                            }
+                            bv[u] = bi[offN[s + k] + seed + pr];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < B; ++u)
+                        if (it0 + u * grp < items) acc = P::add(acc, bv[u]);
+                }
+            }
+            for (int w = grp / 2; w > 0; w >>= 1) acc = P::add(acc, shfl_xor_v(acc, w));
+            if (s == 0) {
+                if (t == 0) sz0 = acc;
+                __syncthreads();
+                ok = P::anchor_of(sz0, &T);
+            }
+            if (lane == 0 && seed < nseed)
+                tile[pad32(tb.seedA[seedoff + seed])] = w2_of(P::to_lin(acc, T));
+        }
+    }
+    __syncthreads();
+
+    // 2. upward zeta on doubles, three layouts as in k_alpha
+    double v[NR];
+    const uint32_t pt = ord8[t];
+    const bool live = __popc(pt) <= d;
+    if (__any(live)) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = dbl_of(tile[pad32((pt << 5) | r)]);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) lin_zeta_up<NR>(v, q);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) tile[pad32((pt << 5) | r)] = w2_of(v[r]);
+    }
+    __syncthreads();
+    const uint32_t tlo = t & 31, thi = t >> 5;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v[r] = dbl_of(tile[pad32((thi << 10) | (r << 5) | tlo)]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) lin_zeta_up<NR>(v, q);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) tile[pad32((thi << 10) | (r << 5) | tlo)] = w2_of(v[r]);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v[r] = dbl_of(tile[pad32(r * kThreads + t)]);
+#pragma unroll
+    for (int q = 2; q < 5; ++q) lin_zeta_up<NR>(v, q);
+    // the largest entry is x = 8191 (thread 255, register 31)
+    if (t == kThreads - 1) sfail = (!ok || force_fb || !(v[NR - 1] <= 1.0e300)) ? 1 : 0;
+    __syncthreads();
+    if (sfail) {
+        if (t == 0) fb_push(fb, blockIdx.x);
+        return;
+    }
+
+    // 3. alpha = q(|S|) t(S)
+    const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const uint32_t x = r * kThreads + t;
+        P::store(alpha, base + x, P::from_lin_q(v[r], sq[h + __popc(x)], T), cnt);
     }
 }
 
@@ -674,13 +910,13 @@ __device__ inline uint32_t padx(uint32_t x) { return x + (x >> 4); }
 //   (x = t*16 + r); two LDS transposes move between them.
 //   The entries with at most d ones (Def. 2: Gamma_v(G) is needed for
 //   |G| <= d only) go from registers to Y1_v[seed][Hc_v].
-// Consecutive tiles run on the same XCD so that its L2 merges the 8-byte Y1
-// writes of neighbouring tiles.
 template <class P>
-__global__ void __launch_bounds__(kThreads)
-k_gamma_tile(int n, int d, GammaGeom gg, Tables tb, typename P::Store L, typename P::Store R,
-             const typename P::V *__restrict__ qt, typename P::V *__restrict__ Y1,
-             typename P::V *__restrict__ part) {
+__device__ __forceinline__ void gamma_tile(int n, int d, const GammaGeom &gg, const Tables &tb,
+                                           const typename P::Store &L,
+                                           const typename P::Store &R,
+                                           const typename P::V *__restrict__ qt,
+                                           typename P::V *__restrict__ Y1,
+                                           typename P::V *__restrict__ part, uint32_t H) {
     using V = typename P::V;
     using Raw = typename P::Raw;
     constexpr int bT = 12, NR = 16;
@@ -691,10 +927,6 @@ k_gamma_tile(int n, int d, GammaGeom gg, Tables tb, typename P::Store L, typenam
     __shared__ V sq[32];
     __shared__ uint32_t offT[34], offT1[34];
     const int t = threadIdx.x;
-    const int hbits = n - bT;
-    const uint32_t nblk = 1u << hbits;
-    uint32_t H = blockIdx.x;
-    if (nblk >= 64) H = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
     const uint64_t Hf = (uint64_t)H << bT;
     for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
     for (uint32_t x = t; x < gg.KT; x += kThreads) seedT[x] = tb.seedmask[x];
@@ -846,6 +1078,259 @@ k_gamma_tile(int n, int d, GammaGeom gg, Tables tb, typename P::Store L, typenam
         }
         __syncthreads();
     }
+}
+
+// Consecutive tiles run on the same XCD so that its L2 merges the 8-byte Y1
+// writes of neighbouring tiles.
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_gamma_tile(int n, int d, GammaGeom gg, Tables tb, typename P::Store L, typename P::Store R,
+             const typename P::V *__restrict__ qt, typename P::V *__restrict__ Y1,
+             typename P::V *__restrict__ part) {
+    const uint32_t nblk = 1u << (n - 12);
+    uint32_t H = blockIdx.x;
+    if (nblk >= 64) H = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
+    gamma_tile<P>(n, d, gg, tb, L, R, qt, Y1, part, H);
+}
+
+// Recomputation of the tiles listed by k_gamma_tile_lin (list[0] entries,
+// list[1 + j] = H): the grid walks the list.
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_gamma_tile_fb(int n, int d, GammaGeom gg, Tables tb, typename P::Store L,
+                typename P::Store R, const typename P::V *__restrict__ qt,
+                typename P::V *__restrict__ Y1, typename P::V *__restrict__ part,
+                const uint32_t *list) {
+    const uint32_t ntile = list[0];
+    for (uint32_t it = blockIdx.x; it < ntile; it += gridDim.x) {
+        __syncthreads();
+        gamma_tile<P>(n, d, gg, tb, L, R, qt, Y1, part, list[1 + it]);
+    }
+}
+
+template <int NR>
+__device__ inline void lin_zeta_down(double *g, int q) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if (!((r >> q) & 1)) g[r] += g[r | (1 << q)];
+}
+
+// Linear-tile form of k_gamma_tile (same geometry, layouts and outputs).
+// For endpoint v every needed output Gamma_v(G_L) of the tile is a sum over
+// supersets of G_L that includes g_v(H + top), top = every tile bit but v.
+// So the products are scaled by one power of two (a log offset for the
+// log-space system) that puts g_v(H + top) near 2^-1000, and the downward
+// zeta runs on plain doubles: one FP64 add per step. Products far below
+// g_v(H + top) may lose bits to the subnormal range; that changes no output
+// by more than 2^-60 of itself. If Gamma_v(H + empty), the largest entry,
+// overflows after the scaling, or g_v(H + top) is zero, the endpoint's
+// outputs are not stored and the tile goes to the fallback list: k_gamma_tile
+// recomputes all of its endpoints. force_fb sends every tile there (tests).
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P::Store L,
+                 typename P::Store R, const typename P::V *__restrict__ qt,
+                 typename P::V *__restrict__ Y1, typename P::V *__restrict__ part,
+                 uint32_t *fb) {
+    using V = typename P::V;
+    using Raw = typename P::Raw;
+    using A = typename P::Anchor;
+    constexpr int bT = 12, NR = 16;
+    extern __shared__ unsigned char smem[];
+    double *gb = reinterpret_cast<double *>(smem);             // padded 2^12 entries
+    V *gv = reinterpret_cast<V *>(smem);                       // same slots, as values
+    uint32_t *sbin = reinterpret_cast<uint32_t *>(gb + 4096 + 256);
+    uint32_t *seedT = sbin + 33 * 33;                          // K(12, d) ranked masks
+    __shared__ V sq[32];
+    __shared__ uint32_t offT[34], offT1[34];
+    __shared__ A sT[32];
+    __shared__ int sok[32];
+    __shared__ int sfail;
+    const int t = threadIdx.x;
+    const int hbits = n - bT;
+    const uint32_t nblk = 1u << hbits;
+    uint32_t H = blockIdx.x;
+    if (nblk >= 64) H = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
+    const uint64_t Hf = (uint64_t)H << bT;
+    for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
+    for (uint32_t x = t; x < gg.KT; x += kThreads) seedT[x] = tb.seedmask[x];
+    if (t < n) sq[t] = qt[t];
+    if (t == 0) sfail = force_fb ? 1 : 0;
+    V Lr[NR], Rr[NR];
+    double g[NR];
+    Raw Rv[NR];                               // next endpoint's Rp tile, undecoded
+    const int hpc = __popcll(Hf);
+    {
+        Raw l0[NR], r0[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const uint32_t x = r * kThreads + t;
+            l0[r] = P::load_raw(L, Hf | x);
+            r0[r] = P::load_raw(R, Hf | x);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            Lr[r] = P::decode_raw(l0[r]);
+            Rr[r] = P::decode_raw(r0[r]);
+        }
+    }
+    int vn = bT;                              // next endpoint above the tile, not in H
+    while (vn < n && ((Hf >> vn) & 1)) ++vn;
+    if (vn < n) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) Rv[r] = P::load_raw(R, Hf | (r * kThreads + t) | (1ull << vn));
+    }
+    {   // invariant partials: sum of L(S) Rp(S) over the tile, per |x| (x = r*256 + t)
+        V lr[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) lr[k] = P::zero();
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const V prod = P::mul(Lr[r], Rr[r]);
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+                if (__popc(r) == k) lr[k] = P::add(lr[k], prod);
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) gv[t * 5 + k] = lr[k];
+        __syncthreads();
+        {   // layer l = t / 16 of the tile: 16 lanes x 16 slots, then a lane tree
+            const int l = t >> 4, j = t & 15;
+            V acc = P::zero();
+            if (l <= bT) {
+                for (int u = j; u < kThreads; u += 16) {
+                    const int k = l - __popc(u);
+                    if (k >= 0 && k <= 4) acc = P::add(acc, gv[u * 5 + k]);
+                }
+            }
+            for (int w = 8; w > 0; w >>= 1) acc = P::add(acc, shfl_xor_v(acc, w));
+            if (l <= bT && j == 0) part[(size_t)H * (bT + 1) + l] = acc;
+        }
+    }
+    // scale of endpoint v: g_v at the top of the tile
+    if (t < n) {
+        const int v = t;
+        const uint32_t all = (1u << bT) - 1;
+        int ok = 0;
+        A T{};
+        if (v < bT) {
+            const V a = P::mul(P::mul(sq[hpc + bT - 1], P::load(L, Hf | (all & ~(1u << v)))),
+                               P::load(R, Hf | all));
+            ok = P::anchor_of(a, &T) ? 1 : 0;
+        } else if (!((Hf >> v) & 1)) {
+            const V a = P::mul(P::mul(sq[hpc + bT], P::load(L, Hf | all)),
+                               P::load(R, Hf | all | (1ull << v)));
+            ok = P::anchor_of(a, &T) ? 1 : 0;
+        }
+        sT[v] = T;
+        sok[v] = ok;
+    }
+    __syncthreads();
+    if (t <= d + 1) {
+        offT[t] = Kcount(sbin, bT, t - 1);
+        offT1[t] = Kcount(sbin, bT - 1, t - 1);
+    }
+    const uint32_t tlo = t & 15, thi = t >> 4;
+    for (int v = 0; v < n; ++v) {
+        const bool low = v < bT;
+        if (!low && ((Hf >> v) & 1)) continue;
+        const A T = sT[v];
+        const int okv = sok[v];
+        // ---- g in layout A, as scaled doubles
+        if (low && v < 8) {
+            // partner Rp(S + v) lives in another thread: exchange through LDS
+#pragma unroll
+            for (int r = 0; r < NR; ++r) gv[padx(r * kThreads + t)] = Rr[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const uint32_t x = r * kThreads + t;
+                g[r] = ((x >> v) & 1) ? 0.0
+                                      : P::prod_lin(sq[hpc + __popc(x)], Lr[r],
+                                                    gv[padx(x | (1u << v))], T);
+            }
+            __syncthreads();
+        } else if (low) {
+            // v is register bit q: the partner is register r + 2^q of this thread
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (v - 8 != q) continue;
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    g[r] = ((r >> q) & 1) ? 0.0
+                                          : P::prod_lin(sq[hpc + __popc(r * kThreads + t)],
+                                                        Lr[r], Rr[r | (1 << q)], T);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                g[r] = P::prod_lin(sq[hpc + __popc(r * kThreads + t)], Lr[r],
+                                   P::decode_raw(Rv[r]), T);
+            vn = v + 1;                       // prefetch the next endpoint's Rp tile
+            while (vn < n && ((Hf >> vn) & 1)) ++vn;
+            if (vn < n) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    Rv[r] = P::load_raw(R, Hf | (r * kThreads + t) | (1ull << vn));
+            }
+        }
+        // ---- tile bits 8..11 (layout A)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (v != 8 + q) lin_zeta_down<NR>(g, q);
+        // ---- A -> B, tile bits 4..7
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gb[padx(r * kThreads + t)] = g[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NR; ++r) g[r] = gb[padx((thi << 8) | (r << 4) | tlo)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (v != 4 + q) lin_zeta_down<NR>(g, q);
+        __syncthreads();
+        // ---- B -> C, tile bits 0..3
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gb[padx((thi << 8) | (r << 4) | tlo)] = g[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NR; ++r) g[r] = gb[padx((t << 4) | r)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (v != q) lin_zeta_down<NR>(g, q);
+        // ---- outputs: entries with at most d ones, read back through LDS
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gb[padx((t << 4) | r)] = g[r];
+        __syncthreads();
+        // Gamma_v(H + empty) bounds every entry of the tile
+        const bool fine = okv && gb[padx(0)] <= 1.0e300;
+        if (!fine) {
+            if (t == 0) sfail = 1;
+        } else {
+            const int hv = gg.hv[v];
+            const uint32_t Hc = low ? H : (uint32_t)compress_bit(H, v - bT);
+            V *dst = Y1 + gg.y1off[v];
+            for (uint32_t si = t; si < gg.KT; si += kThreads) {
+                const uint32_t msk = seedT[si];
+                uint32_t rank = si;
+                if (low) {
+                    if ((msk >> v) & 1) continue;
+                    const uint32_t cm = (uint32_t)compress_bit(msk, v);
+                    rank = offT1[__popc(cm)];
+                    int k = 0;
+                    uint32_t rest = cm;
+                    while (rest) {
+                        const int p = __ffs(rest) - 1;
+                        rest &= rest - 1;
+                        rank += C(sbin, p, ++k);
+                    }
+                }
+                dst[((size_t)rank << hv) + Hc] = P::from_lin(gb[padx(msk)], T);
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0 && sfail) fb_push(fb, H);
 }
 
 // ------------------------- a5 + a6: Gamma, in-tile part, tiles of any size
@@ -1269,7 +1754,9 @@ template <class P>
 __global__ void k_finalize(int n, typename P::Store L, typename P::Store R,
                            const typename P::V *__restrict__ layer,
                            const double *__restrict__ resid, const double *__restrict__ gauge_exp,
-                           const unsigned long long *__restrict__ cnt, double *__restrict__ diag) {
+                           const unsigned long long *__restrict__ cnt,
+                           const uint32_t *__restrict__ fbA, const uint32_t *__restrict__ fbG,
+                           double *__restrict__ diag) {
     if (threadIdx.x != 0) return;
     using V = typename P::V;
     const V LV = P::load(L, (1ull << n) - 1);
@@ -1287,6 +1774,7 @@ __global__ void k_finalize(int n, typename P::Store L, typename P::Store R,
     diag[4] = rLR;
     diag[5] = rl;
     diag[6] = re;
+    diag[7] = (double)((fbA ? fbA[0] : 0u) + (fbG ? fbG[0] : 0u));
 }
 
 // -------------------------------------------------------------- launchers
@@ -1343,7 +1831,7 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     hipLaunchKernelGGL(k_prep<P>, dim3(n), dim3(kThreads), 0, st, n, d, a.K,
                        (const uint32_t *)tb.binom, (const double *)a.logp,
                        (const double *)a.log_rho, (const double *)a.log_q, a.gauge, beta, qt,
-                       a.gauge_exp);
+                       a.gauge_exp, a.fbA, a.fbG);
     BN_CHECK_LAUNCH();
     rec(1);
     if (a.bA == 13) {
@@ -1352,11 +1840,27 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
         const int use_prk = (a.K < 65536u && (size_t)(d + 1) * nit * 2 <= 12288) ? 1 : 0;
         const size_t sm = sizeof(V) * (8192 + 256) + 33 * 33 * 4 +
                           (use_prk ? (size_t)(d + 1) * nit * 2 : 0);
-        (void)hipFuncSetAttribute((const void *)k_alpha<P>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha<P>), dim3((unsigned)(n << (N - 13))),
-                           dim3(kThreads), sm, st, n, d, a.K, use_prk, tb, (const V *)beta,
-                           (const V *)qt, alpha, a.cnt);
+        const unsigned nblkA = (unsigned)(n << (N - 13));
+        if (a.lin_mode) {
+            (void)hipFuncSetAttribute((const void *)k_alpha_lin<P>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_lin<P>), dim3(nblkA), dim3(kThreads), sm,
+                               st, n, d, a.K, use_prk, a.lin_mode == 2 ? 1 : 0, tb,
+                               (const V *)beta, (const V *)qt, alpha, a.cnt, a.fbA);
+            BN_CHECK_LAUNCH();
+            // tiles the linear form could not hold: a grid that walks the list
+            (void)hipFuncSetAttribute((const void *)k_alpha_fb<P>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_fb<P>), dim3(std::min(nblkA, 1024u)),
+                               dim3(kThreads), sm, st, n, d, a.K, use_prk, tb, (const V *)beta,
+                               (const V *)qt, alpha, a.cnt, (const uint32_t *)a.fbA);
+        } else {
+            (void)hipFuncSetAttribute((const void *)k_alpha<P>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha<P>), dim3(nblkA), dim3(kThreads), sm, st,
+                               n, d, a.K, use_prk, tb, (const V *)beta, (const V *)qt, alpha,
+                               a.cnt);
+        }
     } else {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_small<P>), dim3((unsigned)n), dim3(kThreads),
                            sizeof(V) << N, st, n, d, a.K, tb, (const V *)beta, (const V *)qt,
@@ -1385,10 +1889,26 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
         const GammaGeom &gg = a.gg;
         if (a.bG == 12) {
             const size_t sm = sizeof(V) * (4096 + 256) + 33 * 33 * 4 + (size_t)gg.KT * 4;
+            const unsigned nblkG = 1u << (n - 12);
             (void)hipFuncSetAttribute((const void *)k_gamma_tile<P>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile<P>), dim3(1u << (n - 12)),
-                               dim3(kThreads), sm, st, n, d, gg, tb, L, R, (const V *)qt, Y1, part);
+            if (a.lin_mode) {
+                (void)hipFuncSetAttribute((const void *)k_gamma_tile_lin<P>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile_lin<P>), dim3(nblkG),
+                                   dim3(kThreads), sm, st, n, d, a.lin_mode == 2 ? 1 : 0, gg, tb,
+                                   L, R, (const V *)qt, Y1, part, a.fbG);
+                BN_CHECK_LAUNCH();
+                rec(7);
+                (void)hipFuncSetAttribute((const void *)k_gamma_tile_fb<P>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile_fb<P>),
+                                   dim3(std::min(nblkG, 1024u)), dim3(kThreads), sm, st, n, d, gg,
+                                   tb, L, R, (const V *)qt, Y1, part, (const uint32_t *)a.fbG);
+            } else {
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile<P>), dim3(nblkG), dim3(kThreads),
+                                   sm, st, n, d, gg, tb, L, R, (const V *)qt, Y1, part);
+            }
         } else {
             const int bT = a.bG;
             const size_t sm = sizeof(V) * ((size_t)1 << bT) + 33 * 33 * 4 + (size_t)gg.KT * 4 +
@@ -1409,7 +1929,7 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
 #undef BN_GTILE
         }
         BN_CHECK_LAUNCH();
-        rec(7);
+        if (!(a.bG == 12 && a.lin_mode)) rec(7);
         if (gg.blk1[n] > 0) {
             hipLaunchKernelGGL(k_gamma_high1<P>, dim3(gg.blk1[n]), dim3(kThreads),
                                sizeof(V) << gg.hmax1, st, n, d, a.K, gg, tb, (const V *)Y1, gam);
@@ -1443,7 +1963,8 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     BN_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_finalize<P>, dim3(1), dim3(64), 0, st, n, L, R, (const V *)layer,
                        (const double *)a.resid, (const double *)a.gauge_exp,
-                       (const unsigned long long *)a.cnt, a.diag);
+                       (const unsigned long long *)a.cnt, (const uint32_t *)a.fbA,
+                       (const uint32_t *)a.fbG, a.diag);
     BN_CHECK_LAUNCH();
     rec(6);
     return hipSuccess;

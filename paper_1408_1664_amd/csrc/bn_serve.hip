@@ -154,6 +154,7 @@ class GpuExecutor : public Executor {
         r.rep.max_invariant_residual = hdiag[1];
         r.rep.saturated = (uint64_t)hdiag[2];
         r.rep.flushed = (uint64_t)hdiag[3];
+        r.rep.fallback_tiles = (uint64_t)hdiag[7];
         float ms = 0;
         (void)hipEventElapsedTime(&ms, r.ev0, r.ev1);
         r.rep.ms_total = ms;

@@ -120,6 +120,14 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
             P.aG = std::max(1, std::min(v[3], 12));
         }
     }
+    // Linear tiles for the alpha and Gamma in-tile zetas (with fallback).
+    // BN_LINEAR_TILES=0 turns them off, =force sends every tile to the
+    // fallback path (tests of that path).
+    P.lin_mode = 1;
+    if (const char *lt = getenv("BN_LINEAR_TILES")) {
+        if (!strcmp(lt, "0")) P.lin_mode = 0;
+        else if (!strcmp(lt, "force")) P.lin_mode = 2;
+    }
     P.KG = (uint32_t)kcount_u64(P.bG, d);
     P.KA = (uint32_t)kcount_u64(P.aG, d);
     P.W = std::max(std::max(P.bA, P.bG), P.aG);
@@ -200,6 +208,8 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.o_gam = take((size_t)n * P.K * V);
     P.o_part = take(std::max(((size_t)1 << nh) * (P.bL + 1),
                              n >= 12 ? ((size_t)1 << (n - 12)) * 13 : (size_t)0) * V);
+    P.o_fbA = P.bA == 13 ? take(4 * (1 + ((size_t)n << (N - 13)))) : 0;
+    P.o_fbG = P.bG == 12 ? take(4 * (1 + ((size_t)1 << (n - 12)))) : 0;
     if (with_post) P.o_post = take((size_t)n * n * 8);
     if (with_data) P.o_data = take((size_t)n * (size_t)std::max(m, 1));
     P.total = o;
@@ -302,6 +312,9 @@ bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_d
     a.cnt = reinterpret_cast<unsigned long long *>(ws + P.o_cnt);
     a.tiles_per_layer = P.tiles.data();
     a.gg = P.gg;
+    a.lin_mode = P.lin_mode;
+    a.fbA = P.bA == 13 ? reinterpret_cast<uint32_t *>(ws + P.o_fbA) : nullptr;
+    a.fbG = P.bG == 12 ? reinterpret_cast<uint32_t *>(ws + P.o_fbG) : nullptr;
     hipError_t e;
     if (P.x32) {
         PolX32::Store al{reinterpret_cast<float *>(ws + P.o_alpha_f),
@@ -389,6 +402,7 @@ bn_status edge_posteriors_host(const bn_problem *p, bn_precision prec, double *p
         rep->max_invariant_residual = diag[1];
         rep->saturated = (uint64_t)diag[2];
         rep->flushed = (uint64_t)diag[3];
+        rep->fallback_tiles = (uint64_t)diag[7];
         float ms[7] = {0};
         for (int k = 1; k < 7; ++k) (void)hipEventElapsedTime(&ms[k], ev.ev[k - 1], ev.ev[k]);
         float tot = 0;

@@ -128,6 +128,47 @@ def test_every_tiling_path(tiles, prec, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["1", "force", "0"])
+def test_linear_tiles_and_fallback(mode, prec, monkeypatch):
+    """The alpha and Gamma in-tile zetas run on scaled doubles and hand the
+    tiles whose range does not fit to the number-system kernels. 'force'
+    sends every tile down that path, '0' turns the linear form off; all three
+    must agree with the oracle. n = 20 uses 13-bit alpha tiles (64 per node)
+    and 12-bit Gamma tiles (256)."""
+    monkeypatch.setenv("BN_LINEAR_TILES", mode)
+    ds, p = datagen.workload("n20_ternary_m1000_d4")
+    ref = _oracle(ds, p["d"], p["ess"])
+    post, rep = bn.edge_posteriors(ds.data, ds.arity, p["d"], precision=prec, ess=p["ess"])
+    _check(post, rep, ref, prec)
+    n = ds.n
+    want = n * 2 ** (n - 1 - 13) + 2 ** (n - 12) if mode == "force" else 0
+    assert rep["fallback_tiles"] == want
+
+
+def _near_copies(n, m, copies, flip, seed):
+    """Variable 0 uniform; variables 1..copies equal to it except for a
+    fraction `flip` of samples; the rest independent uniform bits."""
+    rng = np.random.default_rng(seed)
+    x = rng.integers(0, 2, size=(n, m)).astype(np.uint8)
+    for j in range(1, copies + 1):
+        x[j] = x[0] ^ (rng.random(m) < flip).astype(np.uint8)
+    return x, np.full(n, 2, dtype=np.uint8)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wide_range_tiles_fall_back(prec):
+    """Near-deterministic copies over 3000 samples make a parent set about
+    2^2700 times likelier than the empty set, beyond what one FP64 scale per
+    tile can hold: those tiles must take the fallback path and the result
+    must still match the oracle."""
+    data, ar = _near_copies(14, 3000, 3, 0.01, seed=11)
+    ref = O.edge_posteriors(data, ar, 3)
+    post, rep = bn.edge_posteriors(data, ar, 3, precision=prec)
+    _check(post, rep, ref, prec)
+    assert rep["fallback_tiles"] > 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_custom_prior_and_k2(prec):
     ds = datagen.random_dag_dataset(10, 400, 3, 3, 1.0, seed=12)
     rng = np.random.default_rng(3)
