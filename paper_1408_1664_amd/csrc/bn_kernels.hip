@@ -1124,8 +1124,13 @@ __device__ inline void lin_zeta_down(double *g, int q) {
 // g_v(H + top) may lose bits to the subnormal range; that changes no output
 // by more than 2^-60 of itself. If Gamma_v(H + empty), the largest entry,
 // overflows after the scaling, or g_v(H + top) is zero, the endpoint's
-// outputs are not stored and the tile goes to the fallback list: k_gamma_tile
-// recomputes all of its endpoints. force_fb sends every tile there (tests).
+// outputs are not stored and the tile goes to the fallback list:
+// k_gamma_tile_fb recomputes all of its endpoints. force_fb sends every tile
+// there (tests).
+// Only L of the tile stays in registers. For every endpoint, tile bit or
+// not, the partners Rp(H + x + v) are streamed from memory (the tile's own
+// Rp for a tile bit, the tile H + v otherwise; both hit in L2), one
+// endpoint ahead of their use.
 template <class P>
 __global__ void __launch_bounds__(kThreads)
 k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P::Store L,
@@ -1156,9 +1161,9 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
     for (uint32_t x = t; x < gg.KT; x += kThreads) seedT[x] = tb.seedmask[x];
     if (t < n) sq[t] = qt[t];
     if (t == 0) sfail = force_fb ? 1 : 0;
-    V Lr[NR], Rr[NR];
+    V Lr[NR];
     double g[NR];
-    Raw Rv[NR];                               // next endpoint's Rp tile, undecoded
+    Raw Rv[NR];                               // partners of the next endpoint, undecoded
     const int hpc = __popcll(Hf);
     {
         Raw l0[NR], r0[NR];
@@ -1168,29 +1173,21 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
             l0[r] = P::load_raw(L, Hf | x);
             r0[r] = P::load_raw(R, Hf | x);
         }
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            Lr[r] = P::decode_raw(l0[r]);
-            Rr[r] = P::decode_raw(r0[r]);
-        }
-    }
-    int vn = bT;                              // next endpoint above the tile, not in H
-    while (vn < n && ((Hf >> vn) & 1)) ++vn;
-    if (vn < n) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r) Rv[r] = P::load_raw(R, Hf | (r * kThreads + t) | (1ull << vn));
-    }
-    {   // invariant partials: sum of L(S) Rp(S) over the tile, per |x| (x = r*256 + t)
+        // invariant partials: sum of L(S) Rp(S) over the tile, per |x| (x = r*256 + t)
         V lr[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) lr[k] = P::zero();
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const V prod = P::mul(Lr[r], Rr[r]);
+            Lr[r] = P::decode_raw(l0[r]);
+            const V prod = P::mul(Lr[r], P::decode_raw(r0[r]));
 #pragma unroll
             for (int k = 0; k < 5; ++k)
                 if (__popc(r) == k) lr[k] = P::add(lr[k], prod);
         }
+        // endpoint 0 (a tile bit): partners Rp(H + x + 1)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) Rv[r] = P::load_raw(R, Hf | (r * kThreads + t) | 1u);
 #pragma unroll
         for (int k = 0; k < 5; ++k) gv[t * 5 + k] = lr[k];
         __syncthreads();
@@ -1236,38 +1233,16 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
         if (!low && ((Hf >> v) & 1)) continue;
         const A T = sT[v];
         const int okv = sok[v];
-        // ---- g in layout A, as scaled doubles
-        if (low && v < 8) {
-            // partner Rp(S + v) lives in another thread: exchange through LDS
+        // ---- g in layout A, as scaled doubles (entries with bit v are not in the lattice)
 #pragma unroll
-            for (int r = 0; r < NR; ++r) gv[padx(r * kThreads + t)] = Rr[r];
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                const uint32_t x = r * kThreads + t;
-                g[r] = ((x >> v) & 1) ? 0.0
-                                      : P::prod_lin(sq[hpc + __popc(x)], Lr[r],
-                                                    gv[padx(x | (1u << v))], T);
-            }
-            __syncthreads();
-        } else if (low) {
-            // v is register bit q: the partner is register r + 2^q of this thread
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (v - 8 != q) continue;
-#pragma unroll
-                for (int r = 0; r < NR; ++r)
-                    g[r] = ((r >> q) & 1) ? 0.0
-                                          : P::prod_lin(sq[hpc + __popc(r * kThreads + t)],
-                                                        Lr[r], Rr[r | (1 << q)], T);
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < NR; ++r)
-                g[r] = P::prod_lin(sq[hpc + __popc(r * kThreads + t)], Lr[r],
-                                   P::decode_raw(Rv[r]), T);
-            vn = v + 1;                       // prefetch the next endpoint's Rp tile
-            while (vn < n && ((Hf >> vn) & 1)) ++vn;
+        for (int r = 0; r < NR; ++r) {
+            const uint32_t x = r * kThreads + t;
+            const double pr = P::prod_lin(sq[hpc + __popc(x)], Lr[r], P::decode_raw(Rv[r]), T);
+            g[r] = (low && ((x >> v) & 1)) ? 0.0 : pr;
+        }
+        {   // partners of the next endpoint
+            int vn = v + 1;
+            while (vn < n && vn >= bT && ((Hf >> vn) & 1)) ++vn;
             if (vn < n) {
 #pragma unroll
                 for (int r = 0; r < NR; ++r)
