@@ -103,6 +103,15 @@ struct PolLog {
     __device__ static inline V from_lin_q(double y, V q, Anchor T) {
         return q > -1e300 ? from_lin(y, T) + q : zero();
     }
+    // binary logarithm (a very negative number for zero)
+    __device__ static inline double log2_of(V x) {
+        return x > -1e300 ? x * 1.4426950408889634074 : -1e300;
+    }
+    // store from_lin(y) * q
+    __device__ static inline void store_lin_q(const Store &s, uint64_t i, double y, V q,
+                                              Anchor T, uint32_t &, uint32_t &) {
+        s.p[i] = from_lin_q(y, q, T);
+    }
 };
 
 // ------------------------------------------------------- FP32 + exponent
@@ -259,6 +268,36 @@ struct PolX32 {
     // from_lin(y) * q
     __device__ static inline V from_lin_q(double y, V q, Anchor T) {
         return from_lin(y * (double)q.f, T + q.e);
+    }
+    // binary logarithm, rounded down (a very negative number for zero)
+    __device__ static inline double log2_of(V x) {
+        if (!(x.f > 0.0f)) return -1e300;
+        return (double)(x.e + ((__float_as_int(x.f) >> 23) & 0xff) - 127);
+    }
+    // Store from_lin(y) * q in the 5-byte form without an intermediate
+    // normalisation; same result and the same saturation / flush rules as
+    // store(), with the counts accumulated in nsat / nfl.
+    __device__ static inline void store_lin_q(const Store &s, uint64_t i, double y, V q,
+                                              Anchor T, uint32_t &nsat, uint32_t &nfl) {
+        const double z = y * (double)q.f;
+        const int k = (__builtin_amdgcn_frexp_exp(z) + 31) >> 6;
+        float f = (float)ldexp(z, -(k << 6));
+        int b = ((T + q.e) >> 6) + k + kX32Bias;
+        const bool zero = !(z > 0.0);
+        const bool fl = !zero && b < 1;
+        const bool sat = !zero && b > 255;
+        nfl += fl ? 1u : 0u;
+        nsat += sat ? 1u : 0u;
+        if (zero || fl) {
+            f = 0.0f;
+            b = 0;
+        }
+        if (sat) {
+            f = 4.0e9f;
+            b = 255;
+        }
+        s.f[i] = f;
+        s.b[i] = (uint8_t)b;
     }
 };
 

@@ -473,20 +473,53 @@ __device__ inline void lin_zeta_up(double *v, int q) {
         if ((r >> q) & 1) v[r] += v[r ^ (1 << q)];
 }
 
-// Linear-tile form of k_alpha (same workgroup geometry, seeds and layouts).
-// Every entry of the tile, alpha_i(H + x) / q, is a sum of seeds that
-// includes Z(empty), so the tile is scaled by one power of two (a log offset
-// for the log-space system) that puts Z(empty) near 2^-1000 and the upward
-// zeta runs on plain doubles: one FP64 add per step instead of an aligned
-// add. Entries far below Z(empty) may lose bits to the subnormal range;
-// that changes no output by more than 2^-60 of itself. If the largest entry
-// (x = all ones, the sum of every seed) overflows the double range, or
-// Z(empty) is zero, the tile stores nothing and goes to the fallback list
-// for k_alpha_fb. force_fb sends every tile there (tests).
+// Per-node scale for the linear alpha tiles. Every alpha_i(S) / q(|S|) is a
+// sum of B_i(G) over G subset S that includes B_i(empty), and none exceeds
+// K(n-1, d) max_G B_i(G). Node i therefore gets one power of two (a log
+// offset for the log-space system) that puts B_i(empty) near 2^-1000, and
+// the node is held in plain doubles when max_G B_i(G) / B_i(empty) is below
+// 2^1900: no partial sum can then leave the double range (K(n-1, d) <
+// 2^31). betal_i(r) = B_i(r) under that scale. Nodes that do not qualify
+// (linok = 0) are computed in the number system proper.
+template <class P>
+__global__ void k_prep_lin(int n, uint32_t K, const typename P::V *__restrict__ beta,
+                           double *__restrict__ betal, typename P::Anchor *__restrict__ anc,
+                           int *__restrict__ linok) {
+    using A = typename P::Anchor;
+    __shared__ double red[kThreads];
+    __shared__ int sok;
+    __shared__ A sT;
+    const int i = blockIdx.x;
+    const int t = threadIdx.x;
+    const typename P::V *bi = beta + (size_t)i * K;
+    double mx = -1e300;
+    for (uint32_t r = t; r < K; r += kThreads) mx = fmax(mx, P::log2_of(bi[r]));
+    mx = block_reduce(mx, red, [](double a, double b) { return fmax(a, b); });
+    if (t == 0) {
+        A T{};
+        const bool ok = P::anchor_of(bi[0], &T) && mx - P::log2_of(bi[0]) <= 1900.0;
+        sok = ok ? 1 : 0;
+        sT = T;
+        anc[i] = T;
+        linok[i] = sok;
+    }
+    __syncthreads();
+    if (!sok) return;
+    const A T = sT;
+    for (uint32_t r = t; r < K; r += kThreads) betal[(size_t)i * K + r] = P::to_lin(bi[r], T);
+}
+
+// Linear-tile form of k_alpha (same workgroup geometry, seeds and layouts):
+// the seeds are sums of betal (the node's B_i in plain doubles, see
+// k_prep_lin) and the upward zeta runs on doubles, one FP64 add per step.
+// The tile is converted back to the number system as it is stored. Tiles of
+// nodes without a linear scale go to the fallback list for k_alpha_fb;
+// force_fb sends every tile there (tests).
 template <class P>
 __global__ void __launch_bounds__(kThreads)
 k_alpha_lin(int n, int d, uint32_t K, int use_prk, int force_fb, Tables tb,
-            const typename P::V *__restrict__ beta, const typename P::V *__restrict__ qt,
+            const double *__restrict__ betal, const typename P::Anchor *__restrict__ anc,
+            const int *__restrict__ linok, const typename P::V *__restrict__ qt,
             typename P::Store alpha, unsigned long long *cnt, uint32_t *fb) {
     using V = typename P::V;
     using A = typename P::Anchor;
@@ -499,13 +532,16 @@ k_alpha_lin(int n, int d, uint32_t K, int use_prk, int force_fb, Tables tb,
     __shared__ uint32_t offN[34];
     __shared__ V sq[32];
     __shared__ uint8_t ord8[256];
-    __shared__ V sz0;
-    __shared__ int sfail;
     const int N = n - 1;
     const int hA = N - bA;
     const int i = blockIdx.x >> hA;
     const uint32_t H = blockIdx.x & ((1u << hA) - 1);
     const int t = threadIdx.x;
+    if (force_fb || !linok[i]) {
+        if (t == 0) fb_push(fb, blockIdx.x);
+        return;
+    }
+    const A T = anc[i];
     for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
     if (t < hA && ((H >> t) & 1)) hb[__popc(H & ((1u << t) - 1))] = bA + t;
     if (t < n) sq[t] = qt[t];
@@ -544,11 +580,10 @@ k_alpha_lin(int n, int d, uint32_t K, int use_prk, int force_fb, Tables tb,
         }
     }
     __syncthreads();
-    const V *bi = beta + (size_t)i * K;
+    const double *bi = betal + (size_t)i * K;
 
-    // 1. seeds as in k_alpha; Z(empty) first, which fixes the scale
-    A T{};
-    bool ok = true;
+    // 1. seeds as in k_alpha, summed in doubles; every load of a lane is
+    //    issued before the first add
     for (int s = 0; s <= d && s <= bA; ++s) {
         const uint32_t nseed = C(bn, bA, s);
         const uint32_t items = Kcount(bn, h, d - s);
@@ -560,14 +595,15 @@ k_alpha_lin(int n, int d, uint32_t K, int use_prk, int force_fb, Tables tb,
         for (uint32_t base = 0; base < nseed; base += per_round) {
             const uint32_t seed = base + t / grp;
             const int lane = t % grp;
-            V acc = P::zero();
+            double acc = 0.0;
             if (seed < nseed) {
-                constexpr int B = 4;
+                constexpr int B = 16;
                 for (uint32_t it0 = lane; it0 < items; it0 += B * grp) {
-                    V bv[B];
+                    double bv[B];
 #pragma unroll
                     for (int u = 0; u < B; ++u) {
                         const uint32_t it = it0 + u * grp;
+                        bv[u] = 0.0;
                         if (it < items) {
                             int k = 0;
                             uint32_t off = 1, toff = 0;
@@ -592,18 +628,11 @@ k_alpha_lin(int n, int d, uint32_t K, int use_prk, int force_fb, Tables tb,
                         }
                     }
 #pragma unroll
-                    for (int u = 0; u < B; ++u)
-                        if (it0 + u * grp < items) acc = P::add(acc, bv[u]);
+                    for (int u = 0; u < B; ++u) acc += bv[u];
                 }
             }
-            for (int w = grp / 2; w > 0; w >>= 1) acc = P::add(acc, shfl_xor_v(acc, w));
-            if (s == 0) {
-                if (t == 0) sz0 = acc;
-                __syncthreads();
-                ok = P::anchor_of(sz0, &T);
-            }
-            if (lane == 0 && seed < nseed)
-                tile[pad32(tb.seedA[seedoff + seed])] = w2_of(P::to_lin(acc, T));
+            for (int w = grp / 2; w > 0; w >>= 1) acc += __shfl_xor(acc, w);
+            if (lane == 0 && seed < nseed) tile[pad32(tb.seedA[seedoff + seed])] = w2_of(acc);
         }
     }
     __syncthreads();
@@ -634,20 +663,18 @@ k_alpha_lin(int n, int d, uint32_t K, int use_prk, int force_fb, Tables tb,
     for (int r = 0; r < NR; ++r) v[r] = dbl_of(tile[pad32(r * kThreads + t)]);
 #pragma unroll
     for (int q = 2; q < 5; ++q) lin_zeta_up<NR>(v, q);
-    // the largest entry is x = 8191 (thread 255, register 31)
-    if (t == kThreads - 1) sfail = (!ok || force_fb || !(v[NR - 1] <= 1.0e300)) ? 1 : 0;
-    __syncthreads();
-    if (sfail) {
-        if (t == 0) fb_push(fb, blockIdx.x);
-        return;
-    }
 
-    // 3. alpha = q(|S|) t(S)
+    // 3. alpha = q(|S|) t(S), stored straight from the doubles
     const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
+    uint32_t nsat = 0, nfl = 0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         const uint32_t x = r * kThreads + t;
-        P::store(alpha, base + x, P::from_lin_q(v[r], sq[h + __popc(x)], T), cnt);
+        P::store_lin_q(alpha, base + x, v[r], sq[h + __popc(x)], T, nsat, nfl);
+    }
+    if (cnt && (nsat | nfl)) {
+        if (nsat) atomicAdd(cnt, (unsigned long long)nsat);
+        if (nfl) atomicAdd(cnt + 1, (unsigned long long)nfl);
     }
 }
 
@@ -1817,11 +1844,16 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
                           (use_prk ? (size_t)(d + 1) * nit * 2 : 0);
         const unsigned nblkA = (unsigned)(n << (N - 13));
         if (a.lin_mode) {
+            using A = typename P::Anchor;
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prep_lin<P>), dim3(n), dim3(kThreads), 0, st, n,
+                               a.K, (const V *)beta, a.betal, (A *)a.anc, a.linok);
+            BN_CHECK_LAUNCH();
             (void)hipFuncSetAttribute((const void *)k_alpha_lin<P>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_lin<P>), dim3(nblkA), dim3(kThreads), sm,
                                st, n, d, a.K, use_prk, a.lin_mode == 2 ? 1 : 0, tb,
-                               (const V *)beta, (const V *)qt, alpha, a.cnt, a.fbA);
+                               (const double *)a.betal, (const A *)a.anc, (const int *)a.linok,
+                               (const V *)qt, alpha, a.cnt, a.fbA);
             BN_CHECK_LAUNCH();
             // tiles the linear form could not hold: a grid that walks the list
             (void)hipFuncSetAttribute((const void *)k_alpha_fb<P>,

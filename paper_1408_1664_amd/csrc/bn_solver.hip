@@ -209,6 +209,9 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.o_part = take(std::max(((size_t)1 << nh) * (P.bL + 1),
                              n >= 12 ? ((size_t)1 << (n - 12)) * 13 : (size_t)0) * V);
     P.o_fbA = P.bA == 13 ? take(4 * (1 + ((size_t)n << (N - 13)))) : 0;
+    P.o_betal = P.bA == 13 ? take((size_t)n * P.K * 8) : 0;
+    P.o_anc = take(32 * 8);
+    P.o_linok = take(32 * 4);
     P.o_fbG = P.bG == 12 ? take(4 * (1 + ((size_t)1 << (n - 12)))) : 0;
     if (with_post) P.o_post = take((size_t)n * n * 8);
     if (with_data) P.o_data = take((size_t)n * (size_t)std::max(m, 1));
@@ -315,6 +318,9 @@ bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_d
     a.lin_mode = P.lin_mode;
     a.fbA = P.bA == 13 ? reinterpret_cast<uint32_t *>(ws + P.o_fbA) : nullptr;
     a.fbG = P.bG == 12 ? reinterpret_cast<uint32_t *>(ws + P.o_fbG) : nullptr;
+    a.betal = P.bA == 13 ? reinterpret_cast<double *>(ws + P.o_betal) : nullptr;
+    a.anc = ws + P.o_anc;
+    a.linok = reinterpret_cast<int *>(ws + P.o_linok);
     hipError_t e;
     if (P.x32) {
         PolX32::Store al{reinterpret_cast<float *>(ws + P.o_alpha_f),
