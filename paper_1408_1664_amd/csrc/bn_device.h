@@ -299,6 +299,14 @@ struct PolX32 {
         s.f[i] = f;
         s.b[i] = (uint8_t)b;
     }
+    // Conversion of many values under one scale: lin_encode gives the
+    // significand and the unbiased exponent byte minus T/64 (no range
+    // checks); the byte is then b = e + T/64 + bias.
+    __device__ static inline float lin_encode(double z, int *e) {
+        const int k = (__builtin_amdgcn_frexp_exp(z) + 31) >> 6;
+        *e = k;
+        return (float)ldexp(z, -(k << 6));
+    }
 };
 
 // -------------------------------------------------------- combinatorics

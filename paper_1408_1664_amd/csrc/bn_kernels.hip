@@ -460,6 +460,17 @@ __device__ inline double dbl_of(W2 w) {
     __builtin_memcpy(&x, &w, 8);
     return x;
 }
+// The same, as two separate planes of 32-bit words: every access is then a
+// 32-bit LDS instruction on consecutive or 33-strided words, free of bank
+// conflicts under the pad32 layout.
+__device__ inline void put_w2(uint32_t *lo, uint32_t *hi, uint32_t ix, double x) {
+    const W2 w = w2_of(x);
+    lo[ix] = w.lo;
+    hi[ix] = w.hi;
+}
+__device__ inline double get_w2(const uint32_t *lo, const uint32_t *hi, uint32_t ix) {
+    return dbl_of(W2{lo[ix], hi[ix]});
+}
 
 __device__ inline void fb_push(uint32_t *fb, uint32_t id) {
     const uint32_t k = atomicAdd(fb, 1u);
@@ -509,56 +520,58 @@ __global__ void k_prep_lin(int n, uint32_t K, const typename P::V *__restrict__ 
     for (uint32_t r = t; r < K; r += kThreads) betal[(size_t)i * K + r] = P::to_lin(bi[r], T);
 }
 
-// Linear-tile form of k_alpha (same workgroup geometry, seeds and layouts):
-// the seeds are sums of betal (the node's B_i in plain doubles, see
-// k_prep_lin) and the upward zeta runs on doubles, one FP64 add per step.
-// The tile is converted back to the number system as it is stored. Tiles of
-// nodes without a linear scale go to the fallback list for k_alpha_fb;
-// force_fb sends every tile there (tests).
+// Binomial coefficient for small arguments; folds to a constant when its
+// arguments are compile-time constants.
+__host__ __device__ constexpr uint32_t cbin(int a, int b) {
+    if (b < 0 || b > a) return 0;
+    uint32_t r = 1;
+    for (int k = 1; k <= b; ++k) r = r * (uint32_t)(a - b + k) / (uint32_t)k;
+    return r;
+}
+
+// Colex rank of the set bits of a 5-bit mask (bit p is element p).
+__host__ __device__ constexpr uint32_t colex5(uint32_t r) {
+    uint32_t c = 0;
+    int j = 0;
+    for (int p = 0; p < 5; ++p)
+        if ((r >> p) & 1) c += cbin(p, ++j);
+    return c;
+}
+
+// Seeds of the linear alpha tiles, in a kernel of their own (the gather of
+// k_alpha's first step, at high occupancy). For tile (i, H) and every G_L
+// over the 13 tile bits with |G_L| <= d,
+//   Zs[(i, H)][rank(G_L)] = sum_{G_H subset H, |G_H| <= d - |G_L|} betal_i(G_H + G_L),
+// rank = size, then colex order. For one G_H the G_L of one size s give a
+// contiguous run of ranks of G_H + G_L, so consecutive lanes take
+// consecutive G_L (coalesced loads) and groups of lanes split the G_H;
+// their partial sums meet in LDS in a fixed order.
 template <class P>
 __global__ void __launch_bounds__(kThreads)
-k_alpha_lin(int n, int d, uint32_t K, int use_prk, int force_fb, Tables tb,
-            const double *__restrict__ betal, const typename P::Anchor *__restrict__ anc,
-            const int *__restrict__ linok, const typename P::V *__restrict__ qt,
-            typename P::Store alpha, unsigned long long *cnt, uint32_t *fb) {
-    using V = typename P::V;
-    using A = typename P::Anchor;
-    constexpr int bA = 13, NR = 32;
+k_alpha_seeds(int n, int d, uint32_t K, uint32_t KS, int use_prk, Tables tb,
+              const double *__restrict__ betal, const int *__restrict__ linok,
+              double *__restrict__ Zs) {
+    constexpr int bA = 13;
     extern __shared__ unsigned char smem[];
-    W2 *tile = reinterpret_cast<W2 *>(smem);                       // pad32(2^13)
-    uint32_t *sbin = reinterpret_cast<uint32_t *>(tile + 8192 + 256);
+    uint32_t *sbin = reinterpret_cast<uint32_t *>(smem);
     uint16_t *prk = reinterpret_cast<uint16_t *>(sbin + 33 * 33);  // (d+1) x items
     __shared__ int hb[32];
     __shared__ uint32_t offN[34];
-    __shared__ V sq[32];
-    __shared__ uint8_t ord8[256];
+    __shared__ double part[kThreads];
     const int N = n - 1;
     const int hA = N - bA;
     const int i = blockIdx.x >> hA;
     const uint32_t H = blockIdx.x & ((1u << hA) - 1);
     const int t = threadIdx.x;
-    if (force_fb || !linok[i]) {
-        if (t == 0) fb_push(fb, blockIdx.x);
-        return;
-    }
-    const A T = anc[i];
+    if (!linok[i]) return;
     for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
     if (t < hA && ((H >> t) & 1)) hb[__popc(H & ((1u << t) - 1))] = bA + t;
-    if (t < n) sq[t] = qt[t];
-    for (uint32_t x = t; x < 8192 + 256; x += kThreads) tile[x] = w2_of(0.0);
     __syncthreads();
     const uint32_t *bn = sbin;
     const int h = __popc(H);
     if (t <= d + 1) offN[t] = Kcount(bn, N, t - 1);
-    {   // ord8: 8-bit patterns by popcount (then value)
-        const int k = __popc(t);
-        uint32_t r = Kcount(bn, 8, k - 1);
-        int j = 0;
-        for (int p = 0; p < 8; ++p)
-            if ((t >> p) & 1) r += C(bn, p, ++j);
-        ord8[r] = (uint8_t)t;
-    }
     const uint32_t nit = Kcount(bn, h, d);
+    uint8_t *itk = reinterpret_cast<uint8_t *>(prk + (use_prk ? (size_t)(d + 1) * nit : 0));
     for (uint32_t it = t; use_prk && it < nit; it += kThreads) {
         int k = 0;
         uint32_t off = 0, toff = 0;
@@ -567,6 +580,7 @@ k_alpha_lin(int n, int d, uint32_t K, int use_prk, int force_fb, Tables tb,
             toff += C(bn, hA, k);
             ++k;
         }
+        itk[it] = (uint8_t)k;
         const uint32_t m = tb.items[toff + (it - off)];
         for (int s = 0; s + k <= d; ++s) {
             uint32_t r = 0, mm = m;
@@ -581,40 +595,37 @@ k_alpha_lin(int n, int d, uint32_t K, int use_prk, int force_fb, Tables tb,
     }
     __syncthreads();
     const double *bi = betal + (size_t)i * K;
-
-    // 1. seeds as in k_alpha, summed in doubles; every load of a lane is
-    //    issued before the first add
+    double *out = Zs + (size_t)blockIdx.x * KS;
     for (int s = 0; s <= d && s <= bA; ++s) {
         const uint32_t nseed = C(bn, bA, s);
         const uint32_t items = Kcount(bn, h, d - s);
-        int grp = 1;
-        while (grp < 64 && (uint32_t)grp < items && (uint32_t)(grp * 2) * nseed <= kThreads)
-            grp *= 2;
-        const uint32_t per_round = kThreads / grp;
         const uint32_t seedoff = Kcount(bn, bA, s - 1);
-        for (uint32_t base = 0; base < nseed; base += per_round) {
-            const uint32_t seed = base + t / grp;
-            const int lane = t % grp;
+        for (uint32_t base = 0; base < nseed; base += kThreads) {
+            const uint32_t cnt = min(nseed - base, (uint32_t)kThreads);
+            const uint32_t ni = kThreads / cnt;        // lanes per seed
+            const uint32_t seed = base + t % cnt, il = t / cnt;
             double acc = 0.0;
-            if (seed < nseed) {
-                constexpr int B = 16;
-                for (uint32_t it0 = lane; it0 < items; it0 += B * grp) {
+            if (il < ni) {
+                constexpr int B = 8;
+                for (uint32_t it0 = il; it0 < items; it0 += B * ni) {
                     double bv[B];
 #pragma unroll
                     for (int u = 0; u < B; ++u) {
-                        const uint32_t it = it0 + u * grp;
+                        const uint32_t it = it0 + u * ni;
                         bv[u] = 0.0;
                         if (it < items) {
-                            int k = 0;
-                            uint32_t off = 1, toff = 0;
-                            while (it >= off) {
-                                toff += C(bn, hA, k);
-                                off += C(bn, h, ++k);
-                            }
+                            int k;
                             uint32_t pr;
                             if (use_prk) {
+                                k = itk[it];
                                 pr = prk[s * nit + it];
                             } else {
+                                k = 0;
+                                uint32_t off = 1, toff = 0;
+                                while (it >= off) {
+                                    toff += C(bn, hA, k);
+                                    off += C(bn, h, ++k);
+                                }
                                 uint32_t m = tb.items[toff + it - (off - C(bn, h, k))];
                                 pr = 0;
                                 int q = 0;
@@ -631,51 +642,202 @@ k_alpha_lin(int n, int d, uint32_t K, int use_prk, int force_fb, Tables tb,
                     for (int u = 0; u < B; ++u) acc += bv[u];
                 }
             }
-            for (int w = grp / 2; w > 0; w >>= 1) acc += __shfl_xor(acc, w);
-            if (lane == 0 && seed < nseed) tile[pad32(tb.seedA[seedoff + seed])] = w2_of(acc);
+            if (ni == 1) {
+                if (il == 0) out[seedoff + seed] = acc;
+            } else {
+                part[t] = acc;
+                __syncthreads();
+                if ((uint32_t)t < cnt) {
+                    double z = 0.0;
+                    for (uint32_t j = 0; j < ni; ++j) z += part[j * cnt + t];
+                    out[seedoff + base + t] = z;
+                }
+                __syncthreads();
+            }
         }
     }
-    __syncthreads();
+}
 
-    // 2. upward zeta on doubles, three layouts as in k_alpha
-    double v[NR];
-    const uint32_t pt = ord8[t];
-    const bool live = __popc(pt) <= d;
-    if (__any(live)) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r) v[r] = dbl_of(tile[pad32((pt << 5) | r)]);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) lin_zeta_up<NR>(v, q);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) tile[pad32((pt << 5) | r)] = w2_of(v[r]);
-    }
-    __syncthreads();
-    const uint32_t tlo = t & 31, thi = t >> 5;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) v[r] = dbl_of(tile[pad32((thi << 10) | (r << 5) | tlo)]);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) lin_zeta_up<NR>(v, q);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < NR; ++r) tile[pad32((thi << 10) | (r << 5) | tlo)] = w2_of(v[r]);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < NR; ++r) v[r] = dbl_of(tile[pad32(r * kThreads + t)]);
-#pragma unroll
-    for (int q = 2; q < 5; ++q) lin_zeta_up<NR>(v, q);
-
-    // 3. alpha = q(|S|) t(S), stored straight from the doubles
-    const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
+// Store NR doubles of a thread (entry r at index base + r * stride, scaled
+// by q(|r| + const), qr indexed by the popcount of r) in the solve's number
+// system. The X32 form checks the exponent range once per thread and takes
+// the per-entry saturation / flush path only when some entry needs it.
+template <class P, int NR>
+__device__ inline void store_tile_lin(const typename P::Store &st, uint64_t base,
+                                      uint32_t stride, const double *v,
+                                      const typename P::V *qr, typename P::Anchor T,
+                                      unsigned long long *cnt) {
     uint32_t nsat = 0, nfl = 0;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const uint32_t x = r * kThreads + t;
-        P::store_lin_q(alpha, base + x, v[r], sq[h + __popc(x)], T, nsat, nfl);
-    }
+    for (int r = 0; r < NR; ++r)
+        P::store_lin_q(st, base + (uint64_t)r * stride, v[r], qr[__builtin_popcount(r)], T,
+                       nsat, nfl);
     if (cnt && (nsat | nfl)) {
         if (nsat) atomicAdd(cnt, (unsigned long long)nsat);
         if (nfl) atomicAdd(cnt + 1, (unsigned long long)nfl);
     }
+}
+
+template <>
+__device__ inline void store_tile_lin<PolX32, 32>(const PolX32::Store &st, uint64_t base,
+                                                  uint32_t stride, const double *v,
+                                                  const X32 *qr, int T,
+                                                  unsigned long long *cnt) {
+    constexpr int NR = 32;
+    float f[NR];
+    int b[NR];
+    bool ok = true;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const X32 q = qr[__builtin_popcount(r)];
+        const double z = v[r] * (double)q.f;
+        int k;
+        f[r] = PolX32::lin_encode(z, &k);
+        b[r] = ((T + q.e) >> 6) + k + kX32Bias;
+        ok = ok && z > 0.0 && b[r] >= 1 && b[r] <= 255;
+    }
+    if (ok) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            st.f[base + (uint64_t)r * stride] = f[r];
+            st.b[base + (uint64_t)r * stride] = (uint8_t)b[r];
+        }
+    } else {
+        uint32_t nsat = 0, nfl = 0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            PolX32::store_lin_q(st, base + (uint64_t)r * stride, v[r], qr[__builtin_popcount(r)],
+                                T, nsat, nfl);
+        if (cnt && (nsat | nfl)) {
+            if (nsat) atomicAdd(cnt, (unsigned long long)nsat);
+            if (nfl) atomicAdd(cnt + 1, (unsigned long long)nfl);
+        }
+    }
+}
+
+// Linear-tile form of k_alpha (same workgroup geometry and layouts). The
+// seeds come from k_alpha_seeds, already as doubles under the node's scale
+// (k_prep_lin), and the upward zeta runs on doubles: one FP64 add per step.
+// Layout A (x = pattern * 32 + r) reads each live thread's seeds straight
+// from Zs; an entry is a seed when it has at most d ones. Layout B skips the
+// entries that are still structural zeros (more than d ones among tile bits
+// 5..12), so the LDS tile never needs clearing. The tile is converted back
+// to the number system as it is stored. Tiles of nodes without a linear
+// scale go to the fallback list for k_alpha_fb; force_fb sends every tile
+// there (tests).
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_alpha_lin(int n, int d, uint32_t KS, int force_fb, const double *__restrict__ Zs,
+            const typename P::Anchor *__restrict__ anc, const int *__restrict__ linok,
+            const typename P::V *__restrict__ qt, typename P::Store alpha,
+            unsigned long long *cnt, uint32_t *fb) {
+    using V = typename P::V;
+    using A = typename P::Anchor;
+    constexpr int bA = 13, NR = 32;
+    extern __shared__ unsigned char smem[];
+    // the tile's doubles as two planes of 32-bit words (pad32 indices)
+    uint32_t *tlo_ = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *thi_ = tlo_ + 8192 + 256;
+    __shared__ V sq[32];
+    __shared__ uint8_t ord8[256];
+    __shared__ uint16_t cb[14 * 14];      // C(a, b), a, b <= 13
+    __shared__ uint32_t k13[15];          // K(13, k - 1) = sum_{j < k} C(13, j)
+    const int N = n - 1;
+    const int hA = N - bA;
+    const int i = blockIdx.x >> hA;
+    const uint32_t H = blockIdx.x & ((1u << hA) - 1);
+    const int t = threadIdx.x;
+    if (force_fb || !linok[i]) {
+        if (t == 0) fb_push(fb, blockIdx.x);
+        return;
+    }
+    const A T = anc[i];
+    if (t < n) sq[t] = qt[t];
+    if (t < 14 * 14) cb[t] = (uint16_t)cbin(t / 14, t % 14);
+    if (t < 15) {
+        uint32_t o = 0;
+        for (int j = 0; j < t; ++j) o += cbin(13, j);
+        k13[t] = o;
+    }
+    __syncthreads();
+    {   // ord8: 8-bit patterns by popcount (then value)
+        const int k = __popc(t);
+        uint32_t r = 0;
+        for (int j = 0; j < k; ++j) r += cb[8 * 14 + j];
+        int j = 0;
+        for (int p = 0; p < 8; ++p)
+            if ((t >> p) & 1) r += cb[p * 14 + (++j)];
+        ord8[r] = (uint8_t)t;
+    }
+    __syncthreads();
+    const int h = __popc(H);
+    const double *zs = Zs + (size_t)blockIdx.x * KS;
+
+    // 1. layout A: x = pt * 32 + r, tile bits 0..4 in registers
+    double v[NR];
+    const uint32_t pt = ord8[t];
+    const int kp = __popc(pt);
+    if (__any(kp <= d)) {
+        // colex contribution of pt's bits (tile bits 5..12), by the number m
+        // of set bits below them
+        uint32_t cpt[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            uint32_t c = 0;
+            int j = m;
+            for (int p = 0; p < 8; ++p)
+                if ((pt >> p) & 1) c += (5 + p >= ++j) ? cb[(5 + p) * 14 + j] : 0u;
+            cpt[m] = c;
+        }
+        uint32_t off13[6];                   // K(13, k - 1) for k = kp + m
+#pragma unroll
+        for (int m = 0; m < 6; ++m) off13[m] = k13[min(kp + m, 14)];
+        // every load is issued (clamped to a valid index) before any is used
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int m = __builtin_popcount(r);
+            const uint32_t idx = (kp + m <= d) ? off13[m] + colex5(r) + cpt[m] : 0u;
+            v[r] = zs[idx];
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            if (kp + __builtin_popcount(r) > d) v[r] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) lin_zeta_up<NR>(v, q);
+        if (kp <= d) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) put_w2(tlo_, thi_, pad32((pt << 5) | r), v[r]);
+        }
+    }
+    __syncthreads();
+    // 2. layout B: x = thi * 1024 + r * 32 + tlo, tile bits 5..9 in registers
+    const uint32_t tlo = t & 31, thi = t >> 5;
+    const int kh = __popc(thi);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v[r] = get_w2(tlo_, thi_, pad32((thi << 10) | (r << 5) | tlo));
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if (kh + __builtin_popcount(r) > d) v[r] = 0.0;     // slot never written
+#pragma unroll
+    for (int q = 0; q < 5; ++q) lin_zeta_up<NR>(v, q);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) put_w2(tlo_, thi_, pad32((thi << 10) | (r << 5) | tlo), v[r]);
+    __syncthreads();
+    // 3. layout C: x = r * 256 + t, tile bits 10..12 in registers
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v[r] = get_w2(tlo_, thi_, pad32(r * kThreads + t));
+#pragma unroll
+    for (int q = 2; q < 5; ++q) lin_zeta_up<NR>(v, q);
+
+    // 4. alpha = q(|S|) t(S), stored straight from the doubles; |S| = h +
+    //    |t| + |r|, so each thread needs q for six sizes only
+    const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
+    V qr[6];
+    const int ht = h + __popc(t);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) qr[m] = sq[min(ht + m, 31)];
+    store_tile_lin<P, NR>(alpha, base + t, kThreads, v, qr, T, cnt);
 }
 
 // Generic form for lattices smaller than the 13-bit tile (n - 1 < 13): one
@@ -773,7 +935,7 @@ __device__ inline void cross_terms(const typename P::Store &alpha, const typenam
                 P::decode4(ra[u], a);
                 P::decode4(rx[u], x);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) acc[k] = P::add(acc[k], P::mul(a[k], x[k]));
+                for (int k = 0; k < 4; ++k) acc[k] = P::add(acc[k], P::mul_raw(a[k], x[k]));
             }
         }
     }
@@ -819,7 +981,7 @@ k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
                        [&](int i) { return (uint64_t)i * NN + compress_bit((Hf ^ (1ull << i)) | lo, i); },
                        [&](int i) { return (Hf ^ (1ull << i)) | lo; }, acc);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) lt[lo + k] = acc[k];
+        for (int k = 0; k < 4; ++k) lt[lo + k] = P::norm_v(acc[k]);
     }
     __syncthreads();
     for (int l = 1; l <= bL; ++l) {
@@ -831,9 +993,9 @@ k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
                 const int i = __ffs(rest) - 1;
                 rest &= rest - 1;
                 const uint32_t Tm = lo ^ (1u << i);
-                acc = P::add(acc, P::mul(la[i * half + (uint32_t)compress_bit(Tm, i)], lt[Tm]));
+                acc = P::add(acc, P::mul_raw(la[i * half + (uint32_t)compress_bit(Tm, i)], lt[Tm]));
             }
-            lt[lo] = acc;
+            lt[lo] = P::norm_v(acc);
         }
         __syncthreads();
     }
@@ -888,7 +1050,7 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
                        [&](int i) { return (uint64_t)i * NN + compress_bit(Sm, i); },
                        [&](int i) { return Sm | (1ull << i); }, acc);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) lt[lo + k] = acc[k];
+        for (int k = 0; k < 4; ++k) lt[lo + k] = P::norm_v(acc[k]);
     }
     __syncthreads();
     for (int l = bL - 1; l >= 0; --l) {
@@ -899,10 +1061,10 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
             while (rest) {
                 const int i = __ffs(rest) - 1;
                 rest &= rest - 1;
-                acc = P::add(acc, P::mul(la[i * half + (uint32_t)compress_bit(lo, i)],
-                                         lt[lo | (1u << i)]));
+                acc = P::add(acc, P::mul_raw(la[i * half + (uint32_t)compress_bit(lo, i)],
+                                             lt[lo | (1u << i)]));
             }
-            lt[lo] = acc;
+            lt[lo] = P::norm_v(acc);
         }
         __syncthreads();
     }
@@ -1843,17 +2005,23 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
         const size_t sm = sizeof(V) * (8192 + 256) + 33 * 33 * 4 +
                           (use_prk ? (size_t)(d + 1) * nit * 2 : 0);
         const unsigned nblkA = (unsigned)(n << (N - 13));
-        if (a.lin_mode) {
+        if (a.lin_mode && a.Zs) {
             using A = typename P::Anchor;
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prep_lin<P>), dim3(n), dim3(kThreads), 0, st, n,
                                a.K, (const V *)beta, a.betal, (A *)a.anc, a.linok);
             BN_CHECK_LAUNCH();
+            const size_t smS = 33 * 33 * 4 + (use_prk ? (size_t)(d + 1) * nit * 2 + nit : 0);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_seeds<P>), dim3(nblkA), dim3(kThreads), smS,
+                               st, n, d, a.K, a.KS, use_prk, tb, (const double *)a.betal,
+                               (const int *)a.linok, a.Zs);
+            BN_CHECK_LAUNCH();
+            const size_t smL = sizeof(W2) * (8192 + 256);
             (void)hipFuncSetAttribute((const void *)k_alpha_lin<P>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_lin<P>), dim3(nblkA), dim3(kThreads), sm,
-                               st, n, d, a.K, use_prk, a.lin_mode == 2 ? 1 : 0, tb,
-                               (const double *)a.betal, (const A *)a.anc, (const int *)a.linok,
-                               (const V *)qt, alpha, a.cnt, a.fbA);
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smL);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_lin<P>), dim3(nblkA), dim3(kThreads), smL,
+                               st, n, d, a.KS, a.lin_mode == 2 ? 1 : 0, (const double *)a.Zs,
+                               (const A *)a.anc, (const int *)a.linok, (const V *)qt, alpha,
+                               a.cnt, a.fbA);
             BN_CHECK_LAUNCH();
             // tiles the linear form could not hold: a grid that walks the list
             (void)hipFuncSetAttribute((const void *)k_alpha_fb<P>,

@@ -210,6 +210,13 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
                              n >= 12 ? ((size_t)1 << (n - 12)) * 13 : (size_t)0) * V);
     P.o_fbA = P.bA == 13 ? take(4 * (1 + ((size_t)n << (N - 13)))) : 0;
     P.o_betal = P.bA == 13 ? take((size_t)n * P.K * 8) : 0;
+    // Linear alpha tiles keep their seeds (K(13, d) doubles per tile) in the
+    // workspace when those take at most 16 GiB; otherwise alpha runs in the
+    // number system proper.
+    P.KS = P.bA == 13 ? (uint32_t)kcount_u64(13, d) : 0;
+    const uint64_t zs_bytes = P.bA == 13 ? ((uint64_t)n << (N - 13)) * P.KS * 8 : 0;
+    P.alpha_lin = P.lin_mode != 0 && P.bA == 13 && zs_bytes <= (16ull << 30);
+    P.o_Zs = P.alpha_lin ? take(zs_bytes) : 0;
     P.o_anc = take(32 * 8);
     P.o_linok = take(32 * 4);
     P.o_fbG = P.bG == 12 ? take(4 * (1 + ((size_t)1 << (n - 12)))) : 0;
@@ -321,6 +328,8 @@ bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_d
     a.betal = P.bA == 13 ? reinterpret_cast<double *>(ws + P.o_betal) : nullptr;
     a.anc = ws + P.o_anc;
     a.linok = reinterpret_cast<int *>(ws + P.o_linok);
+    a.Zs = P.alpha_lin ? reinterpret_cast<double *>(ws + P.o_Zs) : nullptr;
+    a.KS = P.KS;
     hipError_t e;
     if (P.x32) {
         PolX32::Store al{reinterpret_cast<float *>(ws + P.o_alpha_f),
