@@ -663,28 +663,27 @@ k_alpha_seeds(int n, int d, uint32_t K, uint32_t KS, int use_prk, Tables tb,
 // system. The X32 form checks the exponent range once per thread and takes
 // the per-entry saturation / flush path only when some entry needs it.
 template <class P, int NR>
-__device__ inline void store_tile_lin(const typename P::Store &st, uint64_t base,
-                                      uint32_t stride, const double *v,
+__device__ inline void store_tile_lin(const typename P::Store &st, uint64_t ubase,
+                                      uint32_t toff, uint32_t stride, const double *v,
                                       const typename P::V *qr, typename P::Anchor T,
                                       unsigned long long *cnt) {
     uint32_t nsat = 0, nfl = 0;
 #pragma unroll
     for (int r = 0; r < NR; ++r)
-        P::store_lin_q(st, base + (uint64_t)r * stride, v[r], qr[__builtin_popcount(r)], T,
-                       nsat, nfl);
+        P::store_lin_q(st, ubase + (toff + (uint32_t)r * stride), v[r],
+                       qr[__builtin_popcount(r)], T, nsat, nfl);
     if (cnt && (nsat | nfl)) {
         if (nsat) atomicAdd(cnt, (unsigned long long)nsat);
         if (nfl) atomicAdd(cnt + 1, (unsigned long long)nfl);
     }
 }
 
-template <>
-__device__ inline void store_tile_lin<PolX32, 32>(const PolX32::Store &st, uint64_t base,
-                                                  uint32_t stride, const double *v,
-                                                  const X32 *qr, int T,
-                                                  unsigned long long *cnt) {
-    constexpr int NR = 32;
-    float f[NR];
+template <int NR>
+__device__ inline void store_tile_lin_x32(const PolX32::Store &st, uint64_t ubase,
+                                          uint32_t toff, uint32_t stride, const double *v,
+                                          const X32 *qr, int T, unsigned long long *cnt) {
+    float *fp = st.f + ubase;           // uniform bases, 32-bit per-thread offsets
+    uint8_t *bp = st.b + ubase;
     int b[NR];
     bool ok = true;
 #pragma unroll
@@ -692,22 +691,20 @@ __device__ inline void store_tile_lin<PolX32, 32>(const PolX32::Store &st, uint6
         const X32 q = qr[__builtin_popcount(r)];
         const double z = v[r] * (double)q.f;
         int k;
-        f[r] = PolX32::lin_encode(z, &k);
+        const float f = PolX32::lin_encode(z, &k);
         b[r] = ((T + q.e) >> 6) + k + kX32Bias;
         ok = ok && z > 0.0 && b[r] >= 1 && b[r] <= 255;
+        fp[toff + (uint32_t)r * stride] = f;      // rewritten below if out of range
     }
     if (ok) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            st.f[base + (uint64_t)r * stride] = f[r];
-            st.b[base + (uint64_t)r * stride] = (uint8_t)b[r];
-        }
+        for (int r = 0; r < NR; ++r) bp[toff + (uint32_t)r * stride] = (uint8_t)b[r];
     } else {
         uint32_t nsat = 0, nfl = 0;
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-            PolX32::store_lin_q(st, base + (uint64_t)r * stride, v[r], qr[__builtin_popcount(r)],
-                                T, nsat, nfl);
+            PolX32::store_lin_q(st, ubase + (toff + (uint32_t)r * stride), v[r],
+                                qr[__builtin_popcount(r)], T, nsat, nfl);
         if (cnt && (nsat | nfl)) {
             if (nsat) atomicAdd(cnt, (unsigned long long)nsat);
             if (nfl) atomicAdd(cnt + 1, (unsigned long long)nfl);
@@ -715,29 +712,139 @@ __device__ inline void store_tile_lin<PolX32, 32>(const PolX32::Store &st, uint6
     }
 }
 
-// Linear-tile form of k_alpha (same workgroup geometry and layouts). The
-// seeds come from k_alpha_seeds, already as doubles under the node's scale
-// (k_prep_lin), and the upward zeta runs on doubles: one FP64 add per step.
-// Layout A (x = pattern * 32 + r) reads each live thread's seeds straight
-// from Zs; an entry is a seed when it has at most d ones. Layout B skips the
-// entries that are still structural zeros (more than d ones among tile bits
-// 5..12), so the LDS tile never needs clearing. The tile is converted back
-// to the number system as it is stored. Tiles of nodes without a linear
-// scale go to the fallback list for k_alpha_fb; force_fb sends every tile
-// there (tests).
+template <>
+__device__ inline void store_tile_lin<PolX32, 16>(const PolX32::Store &st, uint64_t ubase,
+                                                  uint32_t toff, uint32_t stride,
+                                                  const double *v, const X32 *qr, int T,
+                                                  unsigned long long *cnt) {
+    store_tile_lin_x32<16>(st, ubase, toff, stride, v, qr, T, cnt);
+}
+
+// Padded LDS index for 2^12-entry halves: one spare word every 16.
+__device__ inline uint32_t pad16(uint32_t x) { return x + (x >> 4); }
+
+// Colex rank of the set bits of a 4-bit mask (bit p is element p).
+__host__ __device__ constexpr uint32_t colex4(uint32_t r) {
+    uint32_t c = 0;
+    int j = 0;
+    for (int p = 0; p < 4; ++p)
+        if ((r >> p) & 1) c += cbin(p, ++j);
+    return c;
+}
+
+// One 12-bit half of a linear alpha tile (see k_alpha_lin).
+template <class P, int hb>
+__device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__ zs,
+                                               const typename P::V *sq, const uint16_t *cb,
+                                               const uint32_t *k13, uint32_t *tlo_,
+                                               uint32_t *thi_, uint32_t pt, int h,
+                                               uint64_t base, typename P::Anchor T,
+                                               typename P::Store alpha,
+                                               unsigned long long *cnt) {
+    using V = typename P::V;
+    constexpr int NR = 16;
+    const int t = threadIdx.x;
+    const int kp = __popc(pt);
+    const uint32_t tlo = t & 15, thi = t >> 4;
+    const int kh = __popc(thi);
+    double v[NR];
+    // ---- layout A: y = pt * 16 + r, tile bits 0..3. The upper half starts
+    //      from its own seeds plus the lower half's (the zeta step over
+    //      tile bit 12 commutes with the others).
+    if (__any(kp <= d)) {
+        // colex contribution of pt's bits (tile bits 4..11), and of bit 12
+        // in the upper half, by the number m of set bits below them
+        uint32_t cpt[5], cup[5], off[5], offu[5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            uint32_t c = 0;
+            int j = m;
+            for (int p = 0; p < 8; ++p)
+                if ((pt >> p) & 1) c += (4 + p >= ++j) ? cb[(4 + p) * 14 + j] : 0u;
+            cpt[m] = c;
+            cup[m] = c + ((12 >= j + 1) ? cb[12 * 14 + j + 1] : 0u);
+            off[m] = k13[min(kp + m, 14)];
+            offu[m] = k13[min(kp + m + 1, 14)];
+        }
+        // every load is issued (clamped to a valid index) before any is used
+        double u[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int m = __builtin_popcount(r);
+            const uint32_t il = (kp + m <= d) ? off[m] + colex4(r) + cpt[m] : 0u;
+            const uint32_t iu = (hb && kp + m + 1 <= d) ? offu[m] + colex4(r) + cup[m] : 0u;
+            v[r] = zs[il];
+            u[r] = zs[iu];
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int m = __builtin_popcount(r);
+            const double lo = (kp + m <= d) ? v[r] : 0.0;
+            const double up = (hb && kp + m + 1 <= d) ? u[r] : 0.0;
+            v[r] = lo + up;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lin_zeta_up<NR>(v, q);
+        if (kp <= d) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) put_w2(tlo_, thi_, pad16((pt << 4) | r), v[r]);
+        }
+    }
+    __syncthreads();
+    // ---- layout B: y = thi * 256 + r * 16 + tlo, tile bits 4..7
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v[r] = get_w2(tlo_, thi_, pad16((thi << 8) | (r << 4) | tlo));
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if (kh + __builtin_popcount(r) > d) v[r] = 0.0;      // slot never written
+#pragma unroll
+    for (int q = 0; q < 4; ++q) lin_zeta_up<NR>(v, q);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) put_w2(tlo_, thi_, pad16((thi << 8) | (r << 4) | tlo), v[r]);
+    __syncthreads();
+    // ---- layout C: y = r * 256 + t, tile bits 8..11
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v[r] = get_w2(tlo_, thi_, pad16(r * kThreads + t));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) lin_zeta_up<NR>(v, q);
+    // ---- alpha = q(|S|) t(S), |S| = h + hb + |t| + |r|
+    V qr[5];
+    const int ht = h + hb + __popc(t);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) qr[m] = sq[min(ht + m, 31)];
+    store_tile_lin<P, NR>(alpha, base + hb * 4096, t, kThreads, v, qr, T, cnt);
+    __syncthreads();
+}
+
+// Linear-tile form of k_alpha. Workgroup (i, H) = the same 13-bit tile, run
+// as two 12-bit halves x = hb * 4096 + y through one half-size LDS buffer,
+// which lets four workgroups share a CU. The zeta step over tile bit 12 is
+// taken first: the upper half starts from its seeds plus the lower half's.
+// The seeds come from k_alpha_seeds, already as
+// doubles under the node's scale (k_prep_lin), and the upward zeta runs on
+// doubles, one FP64 add per step, in three layouts of a half (256 threads x
+// 16 entries): A, y = pattern * 16 + r (bits 0..3 in registers; patterns of
+// bits 4..11 by popcount, so waves holding only structural zeros skip it),
+// seeds read straight from Zs; B, y = thi * 256 + r * 16 + tlo (bits 4..7),
+// which skips slots that still hold structural zeros, so the LDS buffer never
+// needs clearing; C, y = r * 256 + t (bits 8..11), stored from there. Tiles
+// of nodes without a linear scale go to the fallback list for k_alpha_fb;
+// force_fb sends every tile there (tests).
+// Four workgroups per CU (LDS allows it): registers are capped to match.
 template <class P>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_alpha_lin(int n, int d, uint32_t KS, int force_fb, const double *__restrict__ Zs,
             const typename P::Anchor *__restrict__ anc, const int *__restrict__ linok,
             const typename P::V *__restrict__ qt, typename P::Store alpha,
             unsigned long long *cnt, uint32_t *fb) {
     using V = typename P::V;
     using A = typename P::Anchor;
-    constexpr int bA = 13, NR = 32;
+    constexpr int bA = 13, NR = 16;
     extern __shared__ unsigned char smem[];
-    // the tile's doubles as two planes of 32-bit words (pad32 indices)
+    // a half's doubles as two planes of 32-bit words (pad16 indices)
     uint32_t *tlo_ = reinterpret_cast<uint32_t *>(smem);
-    uint32_t *thi_ = tlo_ + 8192 + 256;
+    uint32_t *thi_ = tlo_ + 4096 + 256;
     __shared__ V sq[32];
     __shared__ uint8_t ord8[256];
     __shared__ uint16_t cb[14 * 14];      // C(a, b), a, b <= 13
@@ -772,72 +879,11 @@ k_alpha_lin(int n, int d, uint32_t KS, int force_fb, const double *__restrict__ 
     __syncthreads();
     const int h = __popc(H);
     const double *zs = Zs + (size_t)blockIdx.x * KS;
-
-    // 1. layout A: x = pt * 32 + r, tile bits 0..4 in registers
-    double v[NR];
-    const uint32_t pt = ord8[t];
-    const int kp = __popc(pt);
-    if (__any(kp <= d)) {
-        // colex contribution of pt's bits (tile bits 5..12), by the number m
-        // of set bits below them
-        uint32_t cpt[6];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            uint32_t c = 0;
-            int j = m;
-            for (int p = 0; p < 8; ++p)
-                if ((pt >> p) & 1) c += (5 + p >= ++j) ? cb[(5 + p) * 14 + j] : 0u;
-            cpt[m] = c;
-        }
-        uint32_t off13[6];                   // K(13, k - 1) for k = kp + m
-#pragma unroll
-        for (int m = 0; m < 6; ++m) off13[m] = k13[min(kp + m, 14)];
-        // every load is issued (clamped to a valid index) before any is used
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int m = __builtin_popcount(r);
-            const uint32_t idx = (kp + m <= d) ? off13[m] + colex5(r) + cpt[m] : 0u;
-            v[r] = zs[idx];
-        }
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-            if (kp + __builtin_popcount(r) > d) v[r] = 0.0;
-#pragma unroll
-        for (int q = 0; q < 5; ++q) lin_zeta_up<NR>(v, q);
-        if (kp <= d) {
-#pragma unroll
-            for (int r = 0; r < NR; ++r) put_w2(tlo_, thi_, pad32((pt << 5) | r), v[r]);
-        }
-    }
-    __syncthreads();
-    // 2. layout B: x = thi * 1024 + r * 32 + tlo, tile bits 5..9 in registers
-    const uint32_t tlo = t & 31, thi = t >> 5;
-    const int kh = __popc(thi);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) v[r] = get_w2(tlo_, thi_, pad32((thi << 10) | (r << 5) | tlo));
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-        if (kh + __builtin_popcount(r) > d) v[r] = 0.0;     // slot never written
-#pragma unroll
-    for (int q = 0; q < 5; ++q) lin_zeta_up<NR>(v, q);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < NR; ++r) put_w2(tlo_, thi_, pad32((thi << 10) | (r << 5) | tlo), v[r]);
-    __syncthreads();
-    // 3. layout C: x = r * 256 + t, tile bits 10..12 in registers
-#pragma unroll
-    for (int r = 0; r < NR; ++r) v[r] = get_w2(tlo_, thi_, pad32(r * kThreads + t));
-#pragma unroll
-    for (int q = 2; q < 5; ++q) lin_zeta_up<NR>(v, q);
-
-    // 4. alpha = q(|S|) t(S), stored straight from the doubles; |S| = h +
-    //    |t| + |r|, so each thread needs q for six sizes only
     const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
-    V qr[6];
-    const int ht = h + __popc(t);
-#pragma unroll
-    for (int m = 0; m < 6; ++m) qr[m] = sq[min(ht + m, 31)];
-    store_tile_lin<P, NR>(alpha, base + t, kThreads, v, qr, T, cnt);
+    const uint32_t pt = ord8[t];
+    alpha_lin_half<P, 0>(d, zs, sq, cb, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
+    alpha_lin_half<P, 1>(d, zs, sq, cb, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
+
 }
 
 // Generic form for lattices smaller than the 13-bit tile (n - 1 < 13): one
@@ -2015,7 +2061,7 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
                                st, n, d, a.K, a.KS, use_prk, tb, (const double *)a.betal,
                                (const int *)a.linok, a.Zs);
             BN_CHECK_LAUNCH();
-            const size_t smL = sizeof(W2) * (8192 + 256);
+            const size_t smL = 8 * (4096 + 256);
             (void)hipFuncSetAttribute((const void *)k_alpha_lin<P>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smL);
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_lin<P>), dim3(nblkA), dim3(kThreads), smL,
