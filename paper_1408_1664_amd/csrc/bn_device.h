@@ -79,6 +79,22 @@ struct PolLog {
         *reinterpret_cast<double2 *>(s.p + i) = make_double2(v[0], v[1]);
         *reinterpret_cast<double2 *>(s.p + i + 2) = make_double2(v[2], v[3]);
     }
+    // Sixteen consecutive entries (i a multiple of 16), undecoded; at16
+    // picks entry k (a compile-time constant after unrolling).
+    struct Raw16 {
+        double2 p[8];
+    };
+    __device__ static inline Raw16 load16_raw(const Store &s, uint64_t i) {
+        Raw16 r;
+        const double2 *src = reinterpret_cast<const double2 *>(s.p + i);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) r.p[k] = src[k];
+        return r;
+    }
+    __device__ static inline V at16(const Raw16 &r, int k) {
+        return (k & 1) ? r.p[k >> 1].y : r.p[k >> 1].x;
+    }
+    __device__ static inline V at16_nz(const Raw16 &r, int k) { return at16(r, k); }
     // Linear tiles: a value x is held as the plain double x * 2^-T (T a
     // natural-log offset here) so that a zeta over the tile costs one FP64
     // add per step. anchor_of places the reference value a at 2^-1000,
@@ -239,6 +255,32 @@ struct PolX32 {
         for (int k = 0; k < 4; ++k) b |= encode(v[k], &f[k], cnt) << (8 * k);
         *reinterpret_cast<float4 *>(s.f + i) = make_float4(f[0], f[1], f[2], f[3]);
         *reinterpret_cast<uint32_t *>(s.b + i) = b;
+    }
+    // Sixteen consecutive entries (i a multiple of 16), undecoded; at16
+    // decodes entry k (a compile-time constant after unrolling). at16_nz
+    // skips the zero test: a stored zero keeps f = 0, so it is exact as a
+    // factor of a product, but not as an operand of add().
+    struct Raw16 {
+        float4 f[4];
+        uint4 b;
+    };
+    __device__ static inline Raw16 load16_raw(const Store &s, uint64_t i) {
+        Raw16 r;
+        const float4 *src = reinterpret_cast<const float4 *>(s.f + i);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r.f[k] = src[k];
+        r.b = *reinterpret_cast<const uint4 *>(s.b + i);
+        return r;
+    }
+    __device__ static inline V at16_nz(const Raw16 &r, int k) {
+        const float4 q = r.f[k >> 2];
+        const float f = (k & 3) == 0 ? q.x : (k & 3) == 1 ? q.y : (k & 3) == 2 ? q.z : q.w;
+        const uint32_t w = (k >> 2) == 0 ? r.b.x : (k >> 2) == 1 ? r.b.y : (k >> 2) == 2 ? r.b.z : r.b.w;
+        return X32{f, (int)(((w >> (8 * (k & 3))) & 0xffu) - kX32Bias) << 6};
+    }
+    __device__ static inline V at16(const Raw16 &r, int k) {
+        const uint32_t w = (k >> 2) == 0 ? r.b.x : (k >> 2) == 1 ? r.b.y : (k >> 2) == 2 ? r.b.z : r.b.w;
+        return ((w >> (8 * (k & 3))) & 0xffu) ? at16_nz(r, k) : zero();
     }
     // Linear tiles: a value x is held as the plain double x * 2^-T, T a
     // multiple of 64, so that a zeta over the tile costs one FP64 add per

@@ -1350,30 +1350,37 @@ __device__ inline void lin_zeta_down(double *g, int q) {
         if (!((r >> q) & 1)) g[r] += g[r | (1 << q)];
 }
 
-// Linear-tile form of k_gamma_tile (same geometry, layouts and outputs).
-// For endpoint v every needed output Gamma_v(G_L) of the tile is a sum over
-// supersets of G_L that includes g_v(H + top), top = every tile bit but v.
-// So the products are scaled by one power of two (a log offset for the
-// log-space system) that puts g_v(H + top) near 2^-1000, and the downward
-// zeta runs on plain doubles: one FP64 add per step. Products far below
-// g_v(H + top) may lose bits to the subnormal range; that changes no output
-// by more than 2^-60 of itself. If Gamma_v(H + empty), the largest entry,
-// overflows after the scaling, or g_v(H + top) is zero, the endpoint's
-// outputs are not stored and the tile goes to the fallback list:
-// k_gamma_tile_fb recomputes all of its endpoints. force_fb sends every tile
-// there (tests).
-// Only L of the tile stays in registers. For every endpoint, tile bit or
-// not, the partners Rp(H + x + v) are streamed from memory (the tile's own
-// Rp for a tile bit, the tile H + v otherwise; both hit in L2), one
-// endpoint ahead of their use.
+// Linear-tile form of k_gamma_tile (same tiles and outputs). For endpoint v
+// every needed output Gamma_v(G_L) of the tile is a sum over supersets of
+// G_L that includes g_v(H + top), top = every tile bit but v. So the
+// products are scaled by one power of two (a log offset for the log-space
+// system) that puts g_v(H + top) near 2^-1000, and the downward zeta runs on
+// plain doubles: one FP64 add per step. Products far below g_v(H + top) may
+// lose bits to the subnormal range; that changes no output by more than
+// 2^-60 of itself. If Gamma_v(H + empty), the largest entry, overflows after
+// the scaling, or g_v(H + top) is zero, the endpoint's outputs are not stored
+// and the tile goes to the fallback list: k_gamma_tile_fb recomputes all of
+// its endpoints. force_fb sends every tile there (tests).
+// Layouts (x the 12 tile bits, 256 threads x 16 entries):
+//   A  x = t * 16 + r      bits 0..3 in registers; products formed here. Each
+//      thread owns 16 consecutive masks, so L, Rp and the partners Rp(x + v)
+//      move as 16-entry vector loads: the thread's own Rp block for a
+//      register bit, the block of thread t + 2^(v-4) for tile bits 4..11,
+//      the tile H + v above the tile; one endpoint ahead of their use.
+//   B  x = thi * 256 + r * 16 + tlo, bits 4..7 in registers;
+//   C  x = r * 256 + p, p the thread's pattern of bits 0..7 (popcount order),
+//      bits 8..11 in registers. Only outputs with at most d ones are needed
+//      and bits 0..7 are final by then, so threads whose pattern has more
+//      than d ones skip C (whole waves for small d).
+// Two waves per SIMD: registers are capped to match (a few spill).
 template <class P>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P::Store L,
                  typename P::Store R, const typename P::V *__restrict__ qt,
                  typename P::V *__restrict__ Y1, typename P::V *__restrict__ part,
                  uint32_t *fb) {
     using V = typename P::V;
-    using Raw = typename P::Raw;
+    using R16 = typename P::Raw16;
     using A = typename P::Anchor;
     constexpr int bT = 12, NR = 16;
     extern __shared__ unsigned char smem[];
@@ -1386,45 +1393,47 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
     __shared__ A sT[32];
     __shared__ int sok[32];
     __shared__ int sfail;
+    __shared__ uint8_t ord8[256];
     const int t = threadIdx.x;
     const int hbits = n - bT;
     const uint32_t nblk = 1u << hbits;
     uint32_t H = blockIdx.x;
     if (nblk >= 64) H = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
     const uint64_t Hf = (uint64_t)H << bT;
+    const uint64_t x0 = Hf | ((uint32_t)t << 4);   // the thread's first mask in layout A
     for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
     for (uint32_t x = t; x < gg.KT; x += kThreads) seedT[x] = tb.seedmask[x];
     if (t < n) sq[t] = qt[t];
     if (t == 0) sfail = force_fb ? 1 : 0;
-    V Lr[NR];
-    double g[NR];
-    Raw Rv[NR];                               // partners of the next endpoint, undecoded
+    R16 Lw, Rown, Rv;                         // own L and Rp blocks; partners of the next endpoint
     const int hpc = __popcll(Hf);
     {
-        Raw l0[NR], r0[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const uint32_t x = r * kThreads + t;
-            l0[r] = P::load_raw(L, Hf | x);
-            r0[r] = P::load_raw(R, Hf | x);
-        }
-        // invariant partials: sum of L(S) Rp(S) over the tile, per |x| (x = r*256 + t)
+        Lw = P::load16_raw(L, x0);
+        Rown = P::load16_raw(R, x0);
+        Rv = Rown;                            // endpoint 0 is a register bit
+        __syncthreads();                      // sbin
+        // invariant partials: sum of L(S) Rp(S) over the tile, per |x|; the
+        // thread's entries have |x| = |t| + |r|
         V lr[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) lr[k] = P::zero();
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            Lr[r] = P::decode_raw(l0[r]);
-            const V prod = P::mul(Lr[r], P::decode_raw(r0[r]));
+            const V prod = P::mul(P::at16(Lw, r), P::at16(Rown, r));
 #pragma unroll
             for (int k = 0; k < 5; ++k)
-                if (__popc(r) == k) lr[k] = P::add(lr[k], prod);
+                if (__builtin_popcount(r) == k) lr[k] = P::add(lr[k], prod);
         }
-        // endpoint 0 (a tile bit): partners Rp(H + x + 1)
-#pragma unroll
-        for (int r = 0; r < NR; ++r) Rv[r] = P::load_raw(R, Hf | (r * kThreads + t) | 1u);
 #pragma unroll
         for (int k = 0; k < 5; ++k) gv[t * 5 + k] = lr[k];
+        {   // ord8: 8-bit patterns by popcount (then value)
+            const int k = __popc(t);
+            uint32_t r = Kcount(sbin, 8, k - 1);
+            int j = 0;
+            for (int p = 0; p < 8; ++p)
+                if ((t >> p) & 1) r += C(sbin, p, ++j);
+            ord8[r] = (uint8_t)t;
+        }
         __syncthreads();
         {   // layer l = t / 16 of the tile: 16 lanes x 16 slots, then a lane tree
             const int l = t >> 4, j = t & 15;
@@ -1457,40 +1466,66 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
         sT[v] = T;
         sok[v] = ok;
     }
-    __syncthreads();
     if (t <= d + 1) {
         offT[t] = Kcount(sbin, bT, t - 1);
         offT1[t] = Kcount(sbin, bT - 1, t - 1);
     }
+    __syncthreads();
+    // q(|S|) for the thread's entries in layout A: |S| = |H| + |t| + |r|
+    V qa[5];
+    {
+        const int ht = hpc + __popc(t);
+#pragma unroll
+        for (int m = 0; m < 5; ++m) qa[m] = sq[min(ht + m, 31)];
+    }
     const uint32_t tlo = t & 15, thi = t >> 4;
+    const uint32_t pc = ord8[t];
+    const bool liveC = __popc(pc) <= d;
     for (int v = 0; v < n; ++v) {
         const bool low = v < bT;
         if (!low && ((Hf >> v) & 1)) continue;
         const A T = sT[v];
         const int okv = sok[v];
-        // ---- g in layout A, as scaled doubles (entries with bit v are not in the lattice)
+        // ---- products in layout A (entries with bit v are not in the lattice)
+        double g[NR];
+        if (v < 4) {
+            // the partner of register r is register r + 2^v of the own block
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const uint32_t x = r * kThreads + t;
-            const double pr = P::prod_lin(sq[hpc + __popc(x)], Lr[r], P::decode_raw(Rv[r]), T);
-            g[r] = (low && ((x >> v) & 1)) ? 0.0 : pr;
-        }
-        {   // partners of the next endpoint
-            int vn = v + 1;
-            while (vn < n && vn >= bT && ((Hf >> vn) & 1)) ++vn;
-            if (vn < n) {
+            for (int q = 0; q < 4; ++q) {
+                if (v != q) continue;
 #pragma unroll
                 for (int r = 0; r < NR; ++r)
-                    Rv[r] = P::load_raw(R, Hf | (r * kThreads + t) | (1ull << vn));
+                    g[r] = ((r >> q) & 1) ? 0.0
+                                          : P::prod_lin(qa[__builtin_popcount(r)],
+                                                        P::at16_nz(Lw, r),
+                                                        P::at16_nz(Rown, r | (1 << q)), T);
+            }
+        } else {
+            const bool excl = low && ((t >> (v - 4)) & 1);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const double pr =
+                    P::prod_lin(qa[__builtin_popcount(r)], P::at16_nz(Lw, r), P::at16_nz(Rv, r), T);
+                g[r] = excl ? 0.0 : pr;
             }
         }
-        // ---- tile bits 8..11 (layout A)
+        {   // partners of the next endpoint (none needed for register bits)
+            int vn = v + 1;
+            while (vn < n && vn >= bT && ((Hf >> vn) & 1)) ++vn;
+            if (vn >= 4 && vn < bT) {
+                // tile bit vn: the block of thread t + 2^(vn-4) (own block if set)
+                Rv = P::load16_raw(R, Hf | ((uint32_t)(t | (1 << (vn - 4))) << 4));
+            } else if (vn >= bT && vn < n) {
+                Rv = P::load16_raw(R, x0 | (1ull << vn));
+            }
+        }
+        // ---- tile bits 0..3 (layout A)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            if (v != 8 + q) lin_zeta_down<NR>(g, q);
+            if (v != q) lin_zeta_down<NR>(g, q);
         // ---- A -> B, tile bits 4..7
 #pragma unroll
-        for (int r = 0; r < NR; ++r) gb[padx(r * kThreads + t)] = g[r];
+        for (int r = 0; r < NR; ++r) gb[padx((t << 4) | r)] = g[r];
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < NR; ++r) g[r] = gb[padx((thi << 8) | (r << 4) | tlo)];
@@ -1498,21 +1533,22 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
         for (int q = 0; q < 4; ++q)
             if (v != 4 + q) lin_zeta_down<NR>(g, q);
         __syncthreads();
-        // ---- B -> C, tile bits 0..3
 #pragma unroll
         for (int r = 0; r < NR; ++r) gb[padx((thi << 8) | (r << 4) | tlo)] = g[r];
         __syncthreads();
+        // ---- B -> C, tile bits 8..11, live patterns only; results stay in place
+        if (liveC) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) g[r] = gb[padx((t << 4) | r)];
+            for (int r = 0; r < NR; ++r) g[r] = gb[padx((r << 8) | pc)];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (v != q) lin_zeta_down<NR>(g, q);
-        // ---- outputs: entries with at most d ones, read back through LDS
+            for (int q = 0; q < 4; ++q)
+                if (v != 8 + q) lin_zeta_down<NR>(g, q);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) gb[padx((r << 8) | pc)] = g[r];
+        }
         __syncthreads();
-#pragma unroll
-        for (int r = 0; r < NR; ++r) gb[padx((t << 4) | r)] = g[r];
-        __syncthreads();
-        // Gamma_v(H + empty) bounds every entry of the tile
+        // ---- outputs: entries with at most d ones, read back through LDS.
+        // Gamma_v(H + empty) bounds every entry of the tile.
         const bool fine = okv && gb[padx(0)] <= 1.0e300;
         if (!fine) {
             if (t == 0) sfail = 1;
