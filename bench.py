@@ -13,6 +13,7 @@ same dataset.
 Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -29,17 +30,17 @@ STORE_BYTES = {"fp32": 5, "fp64": 8}
 
 # Kernels timed alone by the phase timer (one launch each per solve) and the
 # timer entry that brackets each.
-SINGLE_LAUNCH = {"alpha": "k_alpha", "gamma_tile": "k_gamma_tile"}
+SINGLE_LAUNCH = {"alpha_tile": "k_alpha_lin", "gamma_tile": "k_gamma_tile_lin"}
 
 
 def kernel_bytes(phase, n, prec):
-    """Algorithmic HBM bytes of one launch, E bytes per stored value:
-    alpha writes n 2^(n-1) entries; the Gamma in-tile kernel consumes, for
+    """Algorithmic HBM bytes of one launch, E bytes per stored value: the
+    alpha tile kernel writes n 2^(n-1) entries; the Gamma in-tile kernel consumes, for
     every endpoint v and every S not containing v, L(S) and Rp(S+v): 2E per
     (v, S) pair, n 2^(n-1) pairs."""
     E = STORE_BYTES[prec]
     A = n * 2 ** (n - 1)
-    if phase == "alpha":
+    if phase == "alpha_tile":
         return E * A
     if phase == "gamma_tile":
         return 2 * E * A
@@ -82,6 +83,41 @@ def measure(bn, torch, datagen, name, prec, steps, warmup):
     return res
 
 
+def kernel_source_digest():
+    """SHA-256 over the kernel sources: a counter record holds only for the
+    kernels it was taken on."""
+    h = hashlib.sha256()
+    for name in ("bn_kernels.hip", "bn_kernels.h", "bn_device.h"):
+        with open(os.path.join(ROOT, "paper_1408_1664_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel, workload, prec):
+    """HBM bytes per launch of `kernel` from a counter record under profiles/
+    (a line 'traffic-record kernel=... workload=... precision=...
+    source-sha256=... read_bytes=... write_bytes=...', written from two
+    rocprofv3 --pmc runs, FETCH_SIZE then WRITE_SIZE, each scaled by a plain
+    copy of known size), or None when no record matches the current
+    sources."""
+    digest = kernel_source_digest()
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith((".md", ".txt")):
+            continue
+        with open(os.path.join(pdir, name)) as f:
+            for line in f:
+                if "traffic-record" not in line:
+                    continue
+                kv = dict(tok.split("=", 1) for tok in line.split() if "=" in tok)
+                if (kv.get("kernel") == kernel and kv.get("workload") == workload and
+                        kv.get("precision") == prec and kv.get("source-sha256") == digest):
+                    return int(kv["read_bytes"]) + int(kv["write_bytes"])
+    return None
+
+
 def roofline(res):
     """HBM roofline of the dominant single-launch kernel: algorithmic bytes of
     its launch over its HIP-event duration (averaged over the timed steps)."""
@@ -90,7 +126,8 @@ def roofline(res):
     b = kernel_bytes(dom, n, prec)
     ach = b / (ph[dom] * 1e-3) / 1e9
     return dict(kernel=SINGLE_LAUNCH[dom], ms=ph[dom], bound="hbm", achieved=ach,
-                peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None,
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                traffic=counter_traffic(SINGLE_LAUNCH[dom], res["workload"], prec),
                 algorithmic_bytes=b)
 
 
@@ -196,12 +233,17 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES (counter calibration) and exit")
+    ap.add_argument("--source-digest", action="store_true",
+                    help="print the kernel-source digest that counter records carry and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solve is single-GPU (multi-GPU sharding of "
               "the lattice is a design, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.source_digest:
+        print(kernel_source_digest())
+        return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return

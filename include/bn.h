@@ -173,11 +173,14 @@ bn_status bn_edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *d
  *   ms[7] the Gamma in-tile kernel alone (one launch; part of ms[4]): the
  *         products and the zeta over the low tile bits (the recomputation of
  *         fallback tiles, if any, is not included)
+ *   ms[8] the alpha tile kernel alone (one launch; part of ms[1]): the zeta
+ *         over the low tile bits and the store of alpha (its seed gather and
+ *         any fallback tiles are not included)
  */
 typedef struct bn_timer bn_timer;
 bn_status bn_timer_create(bn_timer **timer);
 bn_status bn_timer_destroy(bn_timer *timer);
-bn_status bn_timer_read(const bn_timer *timer, double ms[8]);
+bn_status bn_timer_read(const bn_timer *timer, double ms[9]);
 
 /*
  * Serving: a server thread batches solves of mixed n, m and arity as they

@@ -177,7 +177,8 @@ def edge_posteriors(data, arity, d, precision="fp64", score="bdeu", ess=1.0, log
     return post, rep.as_dict()
 
 
-PHASES = ["scores", "alpha", "forward", "backward", "gamma", "edges", "total", "gamma_tile"]
+PHASES = ["scores", "alpha", "forward", "backward", "gamma", "edges", "total", "gamma_tile",
+          "alpha_tile"]
 
 
 class Timer:
@@ -189,7 +190,7 @@ class Timer:
         self._h = h
 
     def read(self) -> dict:
-        ms = np.zeros(8, dtype=np.float64)
+        ms = np.zeros(9, dtype=np.float64)
         _check(lib().bn_timer_read(self._h, _ptr(ms)), "bn_timer_read")
         return dict(zip(PHASES, ms.tolist()))
 

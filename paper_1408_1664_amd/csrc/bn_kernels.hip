@@ -2100,11 +2100,13 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
             const size_t smL = 8 * (4096 + 256);
             (void)hipFuncSetAttribute((const void *)k_alpha_lin<P>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smL);
+            rec(8);
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_lin<P>), dim3(nblkA), dim3(kThreads), smL,
                                st, n, d, a.KS, a.lin_mode == 2 ? 1 : 0, (const double *)a.Zs,
                                (const A *)a.anc, (const int *)a.linok, (const V *)qt, alpha,
                                a.cnt, a.fbA);
             BN_CHECK_LAUNCH();
+            rec(9);
             // tiles the linear form could not hold: a grid that walks the list
             (void)hipFuncSetAttribute((const void *)k_alpha_fb<P>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
@@ -2114,14 +2116,20 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
         } else {
             (void)hipFuncSetAttribute((const void *)k_alpha<P>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+            rec(8);
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha<P>), dim3(nblkA), dim3(kThreads), sm, st,
                                n, d, a.K, use_prk, tb, (const V *)beta, (const V *)qt, alpha,
                                a.cnt);
+            BN_CHECK_LAUNCH();
+            rec(9);
         }
     } else {
+        rec(8);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_small<P>), dim3((unsigned)n), dim3(kThreads),
                            sizeof(V) << N, st, n, d, a.K, tb, (const V *)beta, (const V *)qt,
                            alpha, a.cnt);
+        BN_CHECK_LAUNCH();
+        rec(9);
     }
     BN_CHECK_LAUNCH();
     rec(2);

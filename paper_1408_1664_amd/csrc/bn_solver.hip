@@ -489,7 +489,7 @@ bn_status bn_edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *d
 bn_status bn_timer_create(bn_timer **timer) {
     if (!timer) return BN_EINVAL;
     bn_timer *t = new bn_timer();
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < 10; ++k) {
         if (hipEventCreate(&t->ev.ev[k]) != hipSuccess) {
             for (int j = 0; j < k; ++j) (void)hipEventDestroy(t->ev.ev[j]);
             delete t;
@@ -502,12 +502,12 @@ bn_status bn_timer_create(bn_timer **timer) {
 
 bn_status bn_timer_destroy(bn_timer *timer) {
     if (!timer) return BN_EINVAL;
-    for (int k = 0; k < 8; ++k) (void)hipEventDestroy(timer->ev.ev[k]);
+    for (int k = 0; k < 10; ++k) (void)hipEventDestroy(timer->ev.ev[k]);
     delete timer;
     return BN_OK;
 }
 
-bn_status bn_timer_read(const bn_timer *timer, double ms[8]) {
+bn_status bn_timer_read(const bn_timer *timer, double ms[9]) {
     if (!timer || !ms) return BN_EINVAL;
     for (int k = 1; k < 7; ++k) {
         float x = 0;
@@ -523,6 +523,10 @@ bn_status bn_timer_read(const bn_timer *timer, double ms[8]) {
     if (hipEventElapsedTime(&gt, timer->ev.ev[4], timer->ev.ev[7]) != hipSuccess)
         return BN_EDEVICE;
     ms[7] = gt;
+    float at = 0;
+    if (hipEventElapsedTime(&at, timer->ev.ev[8], timer->ev.ev[9]) != hipSuccess)
+        return BN_EDEVICE;
+    ms[8] = at;
     return BN_OK;
 }
 
