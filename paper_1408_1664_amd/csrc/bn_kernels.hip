@@ -2024,6 +2024,28 @@ __global__ void k_finalize(int n, typename P::Store L, typename P::Store R,
 }
 
 // -------------------------------------------------------------- launchers
+// Raise a kernel's dynamic LDS limit to what a workgroup may hold (the
+// device's per-block maximum less the kernel's static LDS), once per kernel
+// and process: the limit is an upper bound only, the launch size decides the
+// allocation, and no launch pays for the call.
+template <auto Kernel>
+static void allow_big_lds() {
+    static const bool once = [] {
+        int dev = 0, mx = 0;
+        hipFuncAttributes fa{};
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                hipSuccess &&
+            hipFuncGetAttributes(&fa, (const void *)Kernel) == hipSuccess)
+            (void)hipFuncSetAttribute((const void *)Kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      mx - (int)fa.sharedSizeBytes);
+        (void)hipGetLastError();
+        return true;
+    }();
+    (void)once;
+}
+
 #define BN_CHECK_LAUNCH() \
     do {                                                   \
         hipError_t e_ = hipGetLastError();                 \
@@ -2098,8 +2120,7 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
                                (const int *)a.linok, a.Zs);
             BN_CHECK_LAUNCH();
             const size_t smL = 8 * (4096 + 256);
-            (void)hipFuncSetAttribute((const void *)k_alpha_lin<P>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smL);
+            allow_big_lds<k_alpha_lin<P>>();
             rec(8);
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_lin<P>), dim3(nblkA), dim3(kThreads), smL,
                                st, n, d, a.KS, a.lin_mode == 2 ? 1 : 0, (const double *)a.Zs,
@@ -2108,14 +2129,12 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
             BN_CHECK_LAUNCH();
             rec(9);
             // tiles the linear form could not hold: a grid that walks the list
-            (void)hipFuncSetAttribute((const void *)k_alpha_fb<P>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+            allow_big_lds<k_alpha_fb<P>>();
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_fb<P>), dim3(std::min(nblkA, 1024u)),
                                dim3(kThreads), sm, st, n, d, a.K, use_prk, tb, (const V *)beta,
                                (const V *)qt, alpha, a.cnt, (const uint32_t *)a.fbA);
         } else {
-            (void)hipFuncSetAttribute((const void *)k_alpha<P>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+            allow_big_lds<k_alpha<P>>();
             rec(8);
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha<P>), dim3(nblkA), dim3(kThreads), sm, st,
                                n, d, a.K, use_prk, tb, (const V *)beta, (const V *)qt, alpha,
@@ -2155,18 +2174,15 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
         if (a.bG == 12) {
             const size_t sm = sizeof(V) * (4096 + 256) + 33 * 33 * 4 + (size_t)gg.KT * 4;
             const unsigned nblkG = 1u << (n - 12);
-            (void)hipFuncSetAttribute((const void *)k_gamma_tile<P>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+            allow_big_lds<k_gamma_tile<P>>();
             if (a.lin_mode) {
-                (void)hipFuncSetAttribute((const void *)k_gamma_tile_lin<P>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+                allow_big_lds<k_gamma_tile_lin<P>>();
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile_lin<P>), dim3(nblkG),
                                    dim3(kThreads), sm, st, n, d, a.lin_mode == 2 ? 1 : 0, gg, tb,
                                    L, R, (const V *)qt, Y1, part, a.fbG);
                 BN_CHECK_LAUNCH();
                 rec(7);
-                (void)hipFuncSetAttribute((const void *)k_gamma_tile_fb<P>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+                allow_big_lds<k_gamma_tile_fb<P>>();
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile_fb<P>),
                                    dim3(std::min(nblkG, 1024u)), dim3(kThreads), sm, st, n, d, gg,
                                    tb, L, R, (const V *)qt, Y1, part, (const uint32_t *)a.fbG);
@@ -2181,8 +2197,7 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
             const dim3 g(1u << (n - bT));
             const int RB = bT > 8 ? bT - 8 : 0;
 #define BN_GTILE(rb)                                                                           \
-    (void)hipFuncSetAttribute((const void *)k_gamma_tile_gen<P, rb>,                           \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);            \
+    allow_big_lds<k_gamma_tile_gen<P, rb>>();                                                  \
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile_gen<P, rb>), g, dim3(kThreads), sm, st, n, \
                        d, bT, gg, tb, L, R, (const V *)qt, Y1)
             switch (RB) {

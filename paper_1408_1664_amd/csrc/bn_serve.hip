@@ -24,6 +24,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -56,6 +57,7 @@ struct Req {
     double t_submit = 0, t_admit = 0, t_done = 0;
     // executor state
     void *ws = nullptr, *hpin = nullptr;
+    size_t ws_bytes = 0, hpin_bytes = 0;   // sizes of the (cached) blocks held
     hipStream_t st = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double fake_until = 0;
@@ -77,9 +79,15 @@ class Executor {
 };
 
 // ------------------------------------------------------------ GPU executor
+// Device workspaces, pinned host blocks and events of finished requests are
+// kept for reuse: hipFree synchronises the whole device, which would stall
+// every other stream at each completion. A request takes the smallest cached
+// block that fits and is at most 1.25 times its size; the device cache is
+// trimmed (freed) when a new allocation fails or when it would exceed cap
+// bytes (half the memory budget).
 class GpuExecutor : public Executor {
    public:
-    GpuExecutor(int dev, int nstreams) : dev_(dev) {
+    GpuExecutor(int dev, int nstreams, size_t cap) : dev_(dev), cap_(cap) {
         (void)hipSetDevice(dev_);
         for (int k = 0; k < nstreams; ++k) {
             hipStream_t s;
@@ -90,6 +98,9 @@ class GpuExecutor : public Executor {
     ~GpuExecutor() override {
         (void)hipSetDevice(dev_);
         for (auto s : streams_) (void)hipStreamDestroy(s);
+        trim_device();
+        for (auto &kv : host_cache_) (void)hipHostFree(kv.second);
+        for (auto e : events_) (void)hipEventDestroy(e);
     }
     bool ok() const { return !streams_.empty(); }
     size_t footprint(const Req &r) override {
@@ -99,14 +110,14 @@ class GpuExecutor : public Executor {
         (void)hipSetDevice(dev_);
         const Plan P = make_plan(r.p.n, r.p.d, r.p.m, r.prec, true, true);
         const size_t nn = (size_t)r.p.n * r.p.n, dbytes = (size_t)r.p.n * r.p.m;
-        if (alloc_fails() || hipMalloc(&r.ws, P.total) != hipSuccess) {
+        if (alloc_fails() || !get_device(P.total, &r.ws, &r.ws_bytes)) {
             r.ws = nullptr;
             r.status = BN_ENOMEM;
             return false;
         }
         // pinned host block: post (n*n), diag (16), data (n*m)
-        if (hipHostMalloc(&r.hpin, (nn + 16) * 8 + dbytes + 8) != hipSuccess) {
-            (void)hipFree(r.ws);
+        if (!get_host((nn + 16) * 8 + dbytes + 8, &r.hpin, &r.hpin_bytes)) {
+            put_device(r.ws, r.ws_bytes);
             r.ws = nullptr;
             r.status = BN_ENOMEM;
             return false;
@@ -116,8 +127,8 @@ class GpuExecutor : public Executor {
         uint8_t *hdata = reinterpret_cast<uint8_t *>(hdiag + 16);
         if (dbytes) memcpy(hdata, r.data.data(), dbytes);
         r.st = streams_[next_++ % streams_.size()];
-        (void)hipEventCreate(&r.ev0);
-        (void)hipEventCreate(&r.ev1);
+        r.ev0 = get_event();
+        r.ev1 = get_event();
         char *ws = reinterpret_cast<char *>(r.ws);
         uint8_t *ddata = reinterpret_cast<uint8_t *>(ws + P.o_data);
         double *dpost = reinterpret_cast<double *>(ws + P.o_post);
@@ -162,18 +173,83 @@ class GpuExecutor : public Executor {
         return true;
     }
     void release(Req &r) override {
-        if (r.ev0) (void)hipEventDestroy(r.ev0);
-        if (r.ev1) (void)hipEventDestroy(r.ev1);
-        if (r.hpin) (void)hipHostFree(r.hpin);
-        if (r.ws) (void)hipFree(r.ws);
+        if (r.ev0) events_.push_back(r.ev0);
+        if (r.ev1) events_.push_back(r.ev1);
+        if (r.hpin) host_cache_.emplace(r.hpin_bytes, r.hpin);
+        if (r.ws) put_device(r.ws, r.ws_bytes);
         r.ev0 = r.ev1 = nullptr;
         r.hpin = r.ws = nullptr;
     }
 
    private:
+    static size_t round_up(size_t x, size_t g) { return (x + g - 1) / g * g; }
+    static bool take(std::multimap<size_t, void *> &c, size_t need, void **p, size_t *got) {
+        auto it = c.lower_bound(need);
+        if (it == c.end() || it->first > need + need / 4) return false;
+        *p = it->second;
+        *got = it->first;
+        c.erase(it);
+        return true;
+    }
+    bool get_device(size_t bytes, void **p, size_t *got) {
+        const size_t need = round_up(bytes, (size_t)2 << 20);
+        if (take(dev_cache_, need, p, got)) {
+            dev_cached_ -= *got;
+            return true;
+        }
+        if (hipMalloc(p, need) != hipSuccess) {
+            (void)hipGetLastError();
+            trim_device();
+            if (hipMalloc(p, need) != hipSuccess) {
+                (void)hipGetLastError();
+                return false;
+            }
+        }
+        *got = need;
+        return true;
+    }
+    void put_device(void *p, size_t bytes) {
+        if (dev_cached_ + bytes > cap_) trim_device();
+        if (bytes > cap_) {
+            (void)hipFree(p);
+            return;
+        }
+        dev_cache_.emplace(bytes, p);
+        dev_cached_ += bytes;
+    }
+    void trim_device() {
+        for (auto &kv : dev_cache_) (void)hipFree(kv.second);
+        dev_cache_.clear();
+        dev_cached_ = 0;
+    }
+    bool get_host(size_t bytes, void **p, size_t *got) {
+        const size_t need = round_up(bytes, (size_t)64 << 10);
+        if (take(host_cache_, need, p, got)) return true;
+        if (hipHostMalloc(p, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        *got = need;
+        return true;
+    }
+    hipEvent_t get_event() {
+        if (!events_.empty()) {
+            hipEvent_t e = events_.back();
+            events_.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+
     int dev_;
+    size_t cap_;
     std::vector<hipStream_t> streams_;
     size_t next_ = 0;
+    std::multimap<size_t, void *> dev_cache_, host_cache_;
+    size_t dev_cached_ = 0;
+    std::vector<hipEvent_t> events_;
 };
 
 // ------------------------------------------------------------ CPU executor
@@ -394,7 +470,7 @@ bn_status bn_server_create(size_t mem_budget_bytes, int32_t max_active, void **s
             if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return BN_EDEVICE;
             budget = free_b / 10 * 9;
         }
-        auto *g = new bnk::GpuExecutor(dev, std::min(max_active, 8));
+        auto *g = new bnk::GpuExecutor(dev, std::min(max_active, 8), budget / 2);
         if (!g->ok()) {
             delete g;
             return BN_EDEVICE;
