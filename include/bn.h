@@ -134,6 +134,21 @@ bn_status bn_workspace_bytes(int32_t n, int32_t d, int32_t m, bn_precision prec,
 bn_status bn_edge_posteriors(const bn_problem *p, bn_precision prec, double *post,
                              bn_report *rep);
 
+/*
+ * Posterior of every parent set of every node, P(G_v = G | D) for |G| <= d
+ * (the parent-set feature of Sec. 2.1, Eq. 5: the same Gamma_v as the edge
+ * sums, P(G_v = G | D) = B_v(G) Gamma_v(G) / F(V)). Any feature of one
+ * node's parent set is a sum of these; the edge posterior P(u -> v | D) is
+ * the sum over the sets G containing u.
+ *   ps:   host, n * K(n-1,d) doubles, ps[v*K + r] for the parent set of rank
+ *         r (the ranking of bn_local_scores); each row sums to 1.
+ *   post: host n*n doubles as for bn_edge_posteriors, or NULL.
+ *   rep:  nullable, as for bn_edge_posteriors.
+ * Errors as for bn_edge_posteriors (BN_EINVAL when ps is NULL).
+ */
+bn_status bn_parent_set_posteriors(const bn_problem *p, bn_precision prec, double *ps,
+                                   double *post, bn_report *rep);
+
 struct bn_timer;
 
 /*

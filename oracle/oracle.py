@@ -111,6 +111,18 @@ def posteriors_from_scores(logB: np.ndarray, d: int, log_q=None, dumps: bool = F
     return res
 
 
+def parent_set_posteriors(logB: np.ndarray, d: int, log_q=None, nthreads: int = 0) -> dict:
+    """P(G_v = G | D) for every node v and parent set G (the parent-set
+    feature of Sec. 2.1 put into Eq. 5): the Gamma_v of Eq. 12 weights each
+    B_v(G), P(G_v = G | D) = B_v(G) Gamma_v(G) / F(V). Returns [n, 2^n]
+    full-mask probabilities (0 where G is not a parent set of v), the edge
+    posteriors and log F(V)."""
+    r = posteriors_from_scores(logB, d, log_q=log_q, dumps=True, nthreads=nthreads)
+    w = np.asarray(logB, dtype=np.float64) + r["gamma"]
+    ps = np.where(np.isfinite(w), np.exp(w - r["log_LV"]), 0.0)
+    return dict(ps=ps, post=r["post"], log_LV=r["log_LV"])
+
+
 def edge_posteriors(data: np.ndarray, arity, d: int, kind: int = BDEU, ess: float = 1.0,
                     log_rho=None, log_q=None, nthreads: int = 0) -> dict:
     """Whole method from data. Returns posteriors [u, v], log L(V), residuals, seconds."""

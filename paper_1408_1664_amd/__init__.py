@@ -27,7 +27,8 @@ _PREC = {"fp64": FP64_LOG, "fp64_log": FP64_LOG, FP64_LOG: FP64_LOG,
 _SCORE = {"bdeu": SCORE_BDEU, "k2": SCORE_K2, SCORE_BDEU: SCORE_BDEU, SCORE_K2: SCORE_K2}
 
 EXPORTED = ["bn_num_parent_sets", "bn_local_scores", "bn_workspace_bytes",
-            "bn_edge_posteriors", "bn_edge_posteriors_dev", "bn_timer_create",
+            "bn_edge_posteriors", "bn_parent_set_posteriors", "bn_edge_posteriors_dev",
+            "bn_timer_create",
             "bn_timer_destroy", "bn_timer_read", "bn_server_create", "bn_serve_submit",
             "bn_serve_poll", "bn_server_destroy", "bn_status_string"]
 
@@ -86,6 +87,8 @@ def lib():
         L.bn_workspace_bytes.restype = ctypes.c_int
         L.bn_edge_posteriors.argtypes = [P, ctypes.c_int, P, P]
         L.bn_edge_posteriors.restype = ctypes.c_int
+        L.bn_parent_set_posteriors.argtypes = [P, ctypes.c_int, P, P, P]
+        L.bn_parent_set_posteriors.restype = ctypes.c_int
         L.bn_edge_posteriors_dev.argtypes = [P, ctypes.c_int, P, ctypes.c_size_t, P, P, P, P]
         L.bn_timer_create.argtypes = [P]
         L.bn_timer_create.restype = ctypes.c_int
@@ -175,6 +178,21 @@ def edge_posteriors(data, arity, d, precision="fp64", score="bdeu", ess=1.0, log
     _check(lib().bn_edge_posteriors(h.ref(), _PREC[precision], _ptr(post), ctypes.byref(rep)),
            "bn_edge_posteriors")
     return post, rep.as_dict()
+
+
+def parent_set_posteriors(data, arity, d, precision="fp64", score="bdeu", ess=1.0,
+                          log_rho=None, log_q=None):
+    """P(G_v = G | D) for every node v and parent set G, |G| <= d, as an
+    [n, K(n-1, d)] array in the ranking of local_scores (each row sums to 1),
+    with the edge posteriors and the report: (ps, post, report dict)."""
+    h = _ProblemHold(data, arity, d, score, ess, log_rho, log_q)
+    K = num_parent_sets(h.n, d)
+    ps = np.empty((h.n, K), dtype=np.float64)
+    post = np.empty((h.n, h.n), dtype=np.float64)
+    rep = Report()
+    _check(lib().bn_parent_set_posteriors(h.ref(), _PREC[precision], _ptr(ps), _ptr(post),
+                                          ctypes.byref(rep)), "bn_parent_set_posteriors")
+    return ps, post, rep.as_dict()
 
 
 PHASES = ["scores", "alpha", "forward", "backward", "gamma", "edges", "total", "gamma_tile",

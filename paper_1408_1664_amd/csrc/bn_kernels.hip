@@ -1925,13 +1925,22 @@ template <class P>
 __global__ void __launch_bounds__(kThreads)
 k_edges(int n, uint32_t K, const uint32_t *__restrict__ famask,
         const typename P::V *__restrict__ beta, const typename P::V *__restrict__ gam,
-        typename P::Store L, double *__restrict__ post, double *__restrict__ resid) {
+        typename P::Store L, double *__restrict__ post, double *__restrict__ resid,
+        double *__restrict__ ps) {
     using V = typename P::V;
     __shared__ V red[kThreads];
     const int v = blockIdx.x;
     const int t = threadIdx.x;
     const V LV = P::load(L, (1ull << n) - 1);
     auto add = [](V a, V b) { return P::add(a, b); };
+    // parent-set posteriors P(G_v = G | D) = w_v(G) / L(V), when asked for
+    if (ps) {
+        for (uint32_t r = t; r < K; r += kThreads) {
+            const double lr =
+                P::log_ratio(P::mul(beta[(size_t)v * K + r], gam[(size_t)v * K + r]), LV);
+            ps[(size_t)v * K + r] = (lr > -1e300) ? exp(lr) : 0.0;
+        }
+    }
     for (int u = -1; u < n; ++u) {
         if (u == v) {
             if (t == 0) post[(size_t)u * n + v] = 0.0;
@@ -2227,7 +2236,7 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     rec(5);
     hipLaunchKernelGGL(k_edges<P>, dim3(n), dim3(kThreads), 0, st, n, a.K,
                        (const uint32_t *)tb.famask, (const V *)beta, (const V *)gam, L, a.post,
-                       a.resid);
+                       a.resid, a.ps);
     BN_CHECK_LAUNCH();
     // layer sums of L(S) Rp(S): partials per tile come from the Gamma tile
     // kernel (12-bit tiles) or from k_inv1 (sweep tiles, small lattices)

@@ -30,7 +30,7 @@ struct Plan {
     size_t o_binom, o_lorder, o_loff, o_pat, o_seed, o_famask, o_seedA, o_items, o_arity, o_rho, o_q, o_logp,
         o_beta, o_qt, o_gexp, o_alpha_f, o_alpha_b, o_L_f, o_L_b, o_R_f, o_R_b, o_Y1, o_Y2,
         o_gam, o_part, o_layer, o_resid, o_diag, o_cnt, o_post, o_data, o_scores_end, o_fbA,
-        o_fbG, o_betal, o_anc, o_linok, o_Zs;
+        o_fbG, o_betal, o_anc, o_linok, o_Zs, o_ps;
     uint32_t KS;                  // K(13, d)
     bool alpha_lin;               // linear alpha tiles (seeds in o_Zs)
     size_t total;
@@ -39,6 +39,7 @@ struct Plan {
 bn_status validate(const bn_problem *p, bool host_data, bool check_values);
 Plan make_plan(int n, int d, int m, bn_precision prec, bool with_data, bool with_post);
 bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_data, char *ws,
-                        hipStream_t st, double *dev_post, double *dev_diag, PhaseEvents *ev);
+                        hipStream_t st, double *dev_post, double *dev_diag, PhaseEvents *ev,
+                        double *dev_ps = nullptr);
 
 }  // namespace bnk

@@ -221,6 +221,7 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.o_linok = take(32 * 4);
     P.o_fbG = P.bG == 12 ? take(4 * (1 + ((size_t)1 << (n - 12)))) : 0;
     if (with_post) P.o_post = take((size_t)n * n * 8);
+    if (with_post) P.o_ps = take((size_t)n * P.K * 8);
     if (with_data) P.o_data = take((size_t)n * (size_t)std::max(m, 1));
     P.total = o;
     P.max_bins = 1;
@@ -287,7 +288,8 @@ static bn_status enqueue_scores(const Plan &P, const bn_problem *p, const uint8_
 }
 
 bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_data, char *ws,
-                        hipStream_t st, double *dev_post, double *dev_diag, PhaseEvents *ev) {
+                        hipStream_t st, double *dev_post, double *dev_diag, PhaseEvents *ev,
+                        double *dev_ps) {
     if (ev && ev->ev[0]) HIPCHK(hipEventRecord(ev->ev[0], st));
     bn_status s = enqueue_scores(P, p, dev_data, ws, st);
     if (s != BN_OK) return s;
@@ -317,6 +319,7 @@ bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_d
     a.layer = ws + P.o_layer;
     a.gauge_exp = reinterpret_cast<double *>(ws + P.o_gexp);
     a.post = dev_post;
+    a.ps = dev_ps;
     a.resid = reinterpret_cast<double *>(ws + P.o_resid);
     a.diag = dev_diag ? dev_diag : reinterpret_cast<double *>(ws + P.o_diag);
     a.cnt = reinterpret_cast<unsigned long long *>(ws + P.o_cnt);
@@ -376,10 +379,10 @@ bn_status local_scores_host(const bn_problem *p, double *log_score) {
 }
 
 bn_status edge_posteriors_host(const bn_problem *p, bn_precision prec, double *post,
-                               bn_report *rep) {
+                               bn_report *rep, double *ps) {
     bn_status s = validate(p, true, true);
     if (s != BN_OK) return s;
-    if (!post) return BN_EINVAL;
+    if (!post && !ps) return BN_EINVAL;
     if (prec != BN_FP64_LOG && prec != BN_FP32_SCALED) return BN_EINVAL;
     Plan P = make_plan(p->n, p->d, p->m, prec, true, true);
     size_t free_b = 0, total_b = 0;
@@ -395,16 +398,22 @@ bn_status edge_posteriors_host(const bn_problem *p, bn_precision prec, double *p
     uint8_t *dev_data = reinterpret_cast<uint8_t *>(ws + P.o_data);
     double *dev_post = reinterpret_cast<double *>(ws + P.o_post);
     double *dev_diag = reinterpret_cast<double *>(ws + P.o_diag);
+    double *dev_ps = ps ? reinterpret_cast<double *>(ws + P.o_ps) : nullptr;
     bn_status rs = BN_OK;
     if (P.m > 0 &&
         hipMemcpyAsync(dev_data, p->data, (size_t)P.n * P.m, hipMemcpyHostToDevice, st) !=
             hipSuccess)
         rs = BN_EDEVICE;
     if (rs == BN_OK)
-        rs = enqueue_solve(P, p, dev_data, ws, st, dev_post, dev_diag, timing ? &ev : nullptr);
+        rs = enqueue_solve(P, p, dev_data, ws, st, dev_post, dev_diag, timing ? &ev : nullptr,
+                           dev_ps);
     double diag[16] = {0};
-    if (rs == BN_OK &&
+    if (rs == BN_OK && post &&
         hipMemcpyAsync(post, dev_post, (size_t)P.n * P.n * 8, hipMemcpyDeviceToHost, st) !=
+            hipSuccess)
+        rs = BN_EDEVICE;
+    if (rs == BN_OK && ps &&
+        hipMemcpyAsync(ps, dev_ps, (size_t)P.n * P.K * 8, hipMemcpyDeviceToHost, st) !=
             hipSuccess)
         rs = BN_EDEVICE;
     if (rs == BN_OK &&
@@ -472,7 +481,14 @@ bn_status bn_workspace_bytes(int32_t n, int32_t d, int32_t m, bn_precision prec,
 
 bn_status bn_edge_posteriors(const bn_problem *p, bn_precision prec, double *post,
                              bn_report *rep) {
-    return bnk::edge_posteriors_host(p, prec, post, rep);
+    if (!post) return BN_EINVAL;
+    return bnk::edge_posteriors_host(p, prec, post, rep, nullptr);
+}
+
+bn_status bn_parent_set_posteriors(const bn_problem *p, bn_precision prec, double *ps,
+                                   double *post, bn_report *rep) {
+    if (!ps) return BN_EINVAL;
+    return bnk::edge_posteriors_host(p, prec, post, rep, ps);
 }
 
 struct bn_timer {

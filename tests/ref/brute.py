@@ -114,6 +114,48 @@ def dag_posteriors(logB, d):
     return post, total
 
 
+def dag_parent_posteriors(logB, d):
+    """P(G_v = G | D) by enumerating DAGs (Eqs. 2-4 with q == 1):
+    dict (v, frozenset G) -> probability."""
+    n = len(logB)
+    choices = [list(_subsets_upto([j for j in range(n) if j != i], d)) for i in range(n)]
+    joint = {}
+    total = -math.inf
+    for pa in itertools.product(*choices):
+        if not _is_acyclic(pa):
+            continue
+        lw = math.log(_linear_extensions(pa)) + sum(logB[i][frozenset(pa[i])] for i in range(n))
+        total = _lse([total, lw])
+        for v in range(n):
+            key = (v, frozenset(pa[v]))
+            joint[key] = _lse([joint.get(key, -math.inf), lw])
+    return {k: math.exp(x - total) for k, x in joint.items()}
+
+
+def orders_parent_posteriors(logB, d, log_q=None):
+    """P(G_v = G | D) by summing Eq. 5 over all orders with the feature
+    f = [G_v = G]: dict (v, frozenset G) -> probability."""
+    n = len(logB)
+    lq = (lambda k: 0.0) if log_q is None else (lambda k: float(log_q[k]))
+    joint = {}
+    total = -math.inf
+    for order in itertools.permutations(range(n)):
+        pos = {v: t for t, v in enumerate(order)}
+        logA = []
+        for i in range(n):
+            L = [j for j in range(n) if pos[j] < pos[i]]
+            logA.append(lq(len(L)) + _lse([logB[i][frozenset(G)] for G in _subsets_upto(L, d)]))
+        lw = sum(logA)
+        total = _lse([total, lw])
+        for v in range(n):
+            L = [j for j in range(n) if pos[j] < pos[v]]
+            rest = lw - logA[v] + lq(len(L))
+            for G in _subsets_upto(L, d):
+                key = (v, frozenset(G))
+                joint[key] = _lse([joint.get(key, -math.inf), rest + logB[v][frozenset(G)]])
+    return {k: math.exp(x - total) for k, x in joint.items()}
+
+
 def per_edge_forward(logB, d, log_q=None):
     """Eq. 9 re-run for each edge with B_v masked by [u in G]; divide by F(V)."""
     n = len(logB)

@@ -98,7 +98,8 @@ def test_invalid_problems_rejected_before_device_work(case):
         data = (data * 19).astype(np.uint8)
         kw["d"] = 3   # 20^4 bins > the histogram limit
     for fn in (lambda: bn.local_scores(data, arity, kw["d"], ess=kw["ess"]),
-               lambda: bn.edge_posteriors(data, arity, kw["d"], "fp32", ess=kw["ess"])):
+               lambda: bn.edge_posteriors(data, arity, kw["d"], "fp32", ess=kw["ess"]),
+               lambda: bn.parent_set_posteriors(data, arity, kw["d"], "fp32", ess=kw["ess"])):
         with pytest.raises(bn.BnError) as ei:
             fn()
         assert ei.value.status == bn.BN_EINVAL
@@ -107,3 +108,12 @@ def test_invalid_problems_rejected_before_device_work(case):
 def test_status_strings():
     assert bn.status_string(0) == "ok"
     assert "invalid" in bn.status_string(-1)
+
+
+def test_parent_set_posteriors_needs_an_output():
+    import ctypes
+    data = np.zeros((4, 10), np.uint8)
+    arity = np.full(4, 2, np.uint8)
+    h = bn._ProblemHold(data, arity, 2, "bdeu", 1.0, None, None)
+    st = bn.lib().bn_parent_set_posteriors(h.ref(), 1, None, None, None)
+    assert st == bn.BN_EINVAL

@@ -169,6 +169,26 @@ def test_wide_range_tiles_fall_back(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["n12_binary_m200_d3", "n20_ternary_m1000_d4"])
+def test_parent_set_posteriors_match_oracle(name, prec):
+    """P(G_v = G | D) for every ranked parent set against the oracle; rows
+    sum to 1; the edge posteriors returned alongside equal the edge entry."""
+    ds, p = datagen.workload(name)
+    n, d = ds.n, p["d"]
+    logB = O.full_log_beta(ds.data, ds.arity, d, ess=p["ess"])
+    ref = O.parent_set_posteriors(logB, d)
+    ps, post, rep = bn.parent_set_posteriors(ds.data, ds.arity, d, precision=prec, ess=p["ess"])
+    masks = ranked_masks(n - 1, d)
+    want = np.stack([ref["ps"][v, expand(masks, v)] for v in range(n)])
+    err = np.abs(ps - want).max()
+    print(f"  {prec}: max |dP(G_v = G)| = {err:.3e}", flush=True)
+    assert err <= TOL[prec]
+    np.testing.assert_allclose(ps.sum(axis=1), 1.0, atol=TOL[prec] * 10)
+    alone, _ = bn.edge_posteriors(ds.data, ds.arity, d, precision=prec, ess=p["ess"])
+    assert np.array_equal(post, alone)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_custom_prior_and_k2(prec):
     ds = datagen.random_dag_dataset(10, 400, 3, 3, 1.0, seed=12)
     rng = np.random.default_rng(3)

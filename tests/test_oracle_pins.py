@@ -187,6 +187,37 @@ def test_dag_enumeration(d):
     np.testing.assert_allclose(r["post"], post, atol=1e-12)
 
 
+def _ps_dict_to_full(ps, n):
+    out = np.zeros((n, 1 << n))
+    for (v, G), x in ps.items():
+        out[v, sum(1 << j for j in G)] = x
+    return out
+
+
+@pytest.mark.parametrize("n,d,seed", [(4, 2, 3), (5, 3, 4), (6, 2, 5)])
+def test_parent_set_posteriors_orders_brute_force(n, d, seed):
+    """P(G_v = G | D) against the sum over all orders with the parent-set
+    feature; rows sum to 1 and the edge posteriors are their marginals."""
+    rng = np.random.default_rng(seed)
+    logB = B.random_logB(n, d, rng, scale=3.0)
+    lq = rng.normal(size=n)
+    r = O.parent_set_posteriors(logB, d, log_q=lq)
+    want = _ps_dict_to_full(B.orders_parent_posteriors(B.full_to_dict(logB, n), d, log_q=lq), n)
+    np.testing.assert_allclose(r["ps"], want, atol=1e-12)
+    np.testing.assert_allclose(r["ps"].sum(axis=1), 1.0, atol=1e-12)
+    for u in range(n):
+        has_u = np.array([(G >> u) & 1 for G in range(1 << n)], dtype=bool)
+        np.testing.assert_allclose(r["ps"][:, has_u].sum(axis=1), r["post"][u, :], atol=1e-12)
+
+
+def test_parent_set_posteriors_dag_enumeration():
+    ds = datagen.random_dag_dataset(4, 80, 2, 2, 1.0, seed=41)
+    logB = O.full_log_beta(ds.data, ds.arity, 2)
+    r = O.parent_set_posteriors(logB, 2)
+    want = _ps_dict_to_full(B.dag_parent_posteriors(B.full_to_dict(logB, 4), 2), 4)
+    np.testing.assert_allclose(r["ps"], want, atol=1e-12)
+
+
 def test_per_edge_forward_rerun():
     n, d = 6, 2
     rng = np.random.default_rng(31)
