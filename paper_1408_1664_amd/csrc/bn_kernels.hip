@@ -10,6 +10,7 @@
 // Tiling: a tile is 2^b consecutive masks (the low b bits vary inside a
 // workgroup, the high bits select the tile). Every kernel runs 256 threads.
 #include <algorithm>
+#include <type_traits>
 
 #include "bn_device.h"
 #include "bn_kernels.h"
@@ -813,7 +814,44 @@ __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__
     const int ht = h + hb + __popc(t);
 #pragma unroll
     for (int m = 0; m < 5; ++m) qr[m] = sq[min(ht + m, 31)];
-    store_tile_lin<P, NR>(alpha, base + hb * 4096, t, kThreads, v, qr, T, cnt);
+    if constexpr (std::is_same<P, PolX32>::value) {
+        // Significands go out from layout C (256 B per wave store); the
+        // exponent bytes are transposed through LDS so that each thread
+        // stores 16 consecutive bytes (1 KB per wave store): byte stores of
+        // 64 B per wave would cost partial-line reads and writes in L2.
+        const uint64_t ub = base + hb * 4096;
+        float *fp = alpha.f + ub;
+        uint8_t *bytes = reinterpret_cast<uint8_t *>(tlo_);
+        uint32_t nsat = 0, nfl = 0, bq[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const X32 q = qr[__builtin_popcount(r)];
+            const double z = v[r] * (double)q.f;
+            int k;
+            float f = PolX32::lin_encode(z, &k);
+            int b = ((T + q.e) >> 6) + k + kX32Bias;
+            const bool zero = !(z > 0.0);
+            const bool fl = !zero && b < 1;
+            const bool sat = !zero && b > 255;
+            nfl += fl ? 1u : 0u;
+            nsat += sat ? 1u : 0u;
+            f = (zero || fl) ? 0.0f : (sat ? 4.0e9f : f);
+            b = (zero || fl) ? 0 : (sat ? 255 : b);
+            fp[(uint32_t)(r * kThreads + t)] = f;
+            bq[r] = (uint32_t)b;
+        }
+        __syncthreads();                      // every layout-C read of the planes is done
+#pragma unroll
+        for (int r = 0; r < NR; ++r) bytes[r * kThreads + t] = (uint8_t)bq[r];
+        __syncthreads();
+        reinterpret_cast<uint4 *>(alpha.b + ub)[t] = reinterpret_cast<const uint4 *>(bytes)[t];
+        if (cnt && (nsat | nfl)) {
+            if (nsat) atomicAdd(cnt, (unsigned long long)nsat);
+            if (nfl) atomicAdd(cnt + 1, (unsigned long long)nfl);
+        }
+    } else {
+        store_tile_lin<P, NR>(alpha, base + hb * 4096, t, kThreads, v, qr, T, cnt);
+    }
     __syncthreads();
 }
 
