@@ -2070,6 +2070,117 @@ __global__ void k_finalize(int n, typename P::Store L, typename P::Store R,
     diag[7] = (double)((fbA ? fbA[0] : 0u) + (fbG ? fbG[0] : 0u));
 }
 
+// ------------------------------------------- a1: local scores, binary data
+// All-binary data as two bit planes per variable: plane 1 marks the samples
+// with value 1, plane 0 those with value 0 (a value out of range is in
+// neither, and so ignored, as in k_scores). W 32-bit words per plane.
+__global__ void k_pack2(int n, int m, int W, const uint8_t *__restrict__ data,
+                        uint32_t *__restrict__ bits) {
+    const uint32_t id = blockIdx.x * kThreads + threadIdx.x;
+    if (id >= (uint32_t)(n * W)) return;
+    const int j = id / W, w = id % W;
+    uint32_t one = 0, zero = 0;
+    for (int b = 0; b < 32; ++b) {
+        const int s = w * 32 + b;
+        if (s >= m) break;
+        const uint8_t x = data[(size_t)j * m + s];
+        one |= (uint32_t)(x == 1) << b;
+        zero |= (uint32_t)(x == 0) << b;
+    }
+    bits[((size_t)j * 2 + 1) * W + w] = one;
+    bits[((size_t)j * 2 + 0) * W + w] = zero;
+}
+
+// Counts of one family of k parents over words w = lane, lane + 16, ...:
+// cell (c << 1) | v, c the parents' values as bits, v the child's value, is
+// the popcount of the AND of the matching planes.
+template <int KP>
+__device__ inline void count_cells2(const uint32_t *__restrict__ bits, int W, int lane,
+                                    int child, const int *par, uint32_t *cnt) {
+    constexpr int NC = 2 << KP;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) cnt[c] = 0;
+    for (int w = lane; w < W; w += 16) {
+        uint32_t a[NC];
+        a[0] = bits[((size_t)child * 2 + 0) * W + w];
+        a[1] = bits[((size_t)child * 2 + 1) * W + w];
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+            const uint32_t p0 = bits[((size_t)par[j] * 2 + 0) * W + w];
+            const uint32_t p1 = bits[((size_t)par[j] * 2 + 1) * W + w];
+            const int half = 2 << j;
+#pragma unroll
+            for (int c = 0; c < NC / 2; ++c) {
+                if (c < half) {
+                    a[c + half] = a[c] & p1;
+                    a[c] = a[c] & p0;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) cnt[c] += __popc(a[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int sft = 8; sft > 0; sft >>= 1) cnt[c] += __shfl_xor(cnt[c], sft, 16);
+}
+
+// BDeu / K2 log marginal likelihood of one family from its cell counts
+// (all variables binary: q = 2^k configurations, r = 2 values); the
+// configurations are split over the 16 lanes, partial sums met by a fixed
+// butterfly.
+template <int KP>
+__device__ inline double family_score2(const uint32_t *cnt, int lane, int kind, double ess) {
+    constexpr int Q = 1 << KP;
+    const double q = (double)Q;
+    const double a_j = kind == 0 ? ess / q : 2.0;
+    const double a_jk = kind == 0 ? ess / (2.0 * q) : 1.0;
+    const double lg_aj = lgamma(a_j), lg_ajk = lgamma(a_jk);
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        if ((j & 15) != lane) continue;
+        const uint32_t c0 = cnt[2 * j], c1 = cnt[2 * j + 1];
+        const uint32_t nj = c0 + c1;
+        if (nj) {
+            double s = lg_aj - lgamma(a_j + nj);
+            if (c0) s += lgamma(a_jk + c0) - lg_ajk;
+            if (c1) s += lgamma(a_jk + c1) - lg_ajk;
+            acc += s;
+        }
+    }
+    for (int sft = 8; sft > 0; sft >>= 1) acc += __shfl_xor(acc, sft, 16);
+    return acc;
+}
+
+// Local scores of all-binary data with d <= 4: 16 lanes per family, 16
+// families per workgroup, counts from the bit planes of k_pack2.
+__global__ void __launch_bounds__(kThreads)
+k_scores2(int n, int W, uint32_t K, int kind, double ess, const uint32_t *__restrict__ famask,
+          const uint32_t *__restrict__ bits, double *__restrict__ out) {
+    const int g = threadIdx.x >> 4, lane = threadIdx.x & 15;
+    const uint32_t fam = blockIdx.x * 16 + g;
+    if (fam >= (uint32_t)n * K) return;      // whole 16-lane groups leave together
+    const int i = fam / K;
+    const uint32_t r = fam % K;
+    const uint32_t msk = famask[r];
+    int par[4];
+    int k = 0;
+    for (int p = 0; p < 31 && k < 4; ++p)
+        if ((msk >> p) & 1) par[k++] = p < i ? p : p + 1;
+    uint32_t cnt[32];
+    double sc = 0.0;
+    switch (k) {
+        case 0: count_cells2<0>(bits, W, lane, i, par, cnt); sc = family_score2<0>(cnt, lane, kind, ess); break;
+        case 1: count_cells2<1>(bits, W, lane, i, par, cnt); sc = family_score2<1>(cnt, lane, kind, ess); break;
+        case 2: count_cells2<2>(bits, W, lane, i, par, cnt); sc = family_score2<2>(cnt, lane, kind, ess); break;
+        case 3: count_cells2<3>(bits, W, lane, i, par, cnt); sc = family_score2<3>(cnt, lane, kind, ess); break;
+        default: count_cells2<4>(bits, W, lane, i, par, cnt); sc = family_score2<4>(cnt, lane, kind, ess); break;
+    }
+    if (lane == 0) out[fam] = sc;
+}
+
 // -------------------------------------------------------------- launchers
 // Raise a kernel's dynamic LDS limit to what a workgroup may hold (the
 // device's per-block maximum less the kernel's static LDS), once per kernel
@@ -2118,7 +2229,18 @@ hipError_t launch_setup(const Tables &tb, int bL, int W, int bG, int bA, int d, 
 
 hipError_t launch_scores(int n, int m, const uint8_t *data, const uint8_t *arity, uint32_t K,
                          int kind, double ess, const uint32_t *famask, int max_bins,
-                         double *out, hipStream_t st) {
+                         double *out, hipStream_t st, uint32_t *bits) {
+    if (bits) {
+        // all-binary data, d <= 4: counts from bit planes
+        const int W = (m + 31) / 32;
+        hipLaunchKernelGGL(k_pack2, dim3((unsigned)((n * W + kThreads - 1) / kThreads)),
+                           dim3(kThreads), 0, st, n, m, W, data, bits);
+        BN_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_scores2, dim3((unsigned)((n * K + 15) / 16)), dim3(kThreads), 0, st,
+                           n, W, K, kind, ess, famask, (const uint32_t *)bits, out);
+        BN_CHECK_LAUNCH();
+        return hipSuccess;
+    }
     hipLaunchKernelGGL(k_scores, dim3((unsigned)(n * K)), dim3(kThreads),
                        (size_t)max_bins * sizeof(int), st, n, m, data, arity, K, kind, ess,
                        famask, out);

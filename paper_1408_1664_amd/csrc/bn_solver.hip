@@ -188,6 +188,7 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.o_qt = take(32 * V);
     P.o_gexp = take(64 * 8);
     P.o_logp = take((size_t)n * P.K * 8);
+    P.o_bits = take((size_t)2 * n * ((std::max(m, 1) + 31) / 32) * 4);   // binary bit planes
     // everything the local-score step touches lies below this offset
     P.o_scores_end = o;
     P.o_beta = take((size_t)n * P.K * V);
@@ -281,9 +282,15 @@ static bn_status enqueue_scores(const Plan &P, const bn_problem *p, const uint8_
     Tables tb = tables_of(P, ws);
     HIPCHK(launch_setup(tb, P.bL, P.W, P.bG, P.bA, P.d, P.N, P.K, st));
     const int kind = p->score == BN_SCORE_K2 ? 1 : 0;
+    // all-binary data with d <= 4: the bit-plane counting path
+    bool binary = P.m > 0 && P.d <= 4;
+    for (int i = 0; i < P.n && binary; ++i) binary = p->arity[i] == 2;
+    if (const char *e = getenv("BN_SCORE_BITS"))
+        if (e[0] == '0') binary = false;
     HIPCHK(launch_scores(P.n, P.m, dev_data, reinterpret_cast<const uint8_t *>(ws + P.o_arity), P.K,
                          kind, p->ess, tb.famask, max_bins_of(p, P.d),
-                         reinterpret_cast<double *>(ws + P.o_logp), st));
+                         reinterpret_cast<double *>(ws + P.o_logp), st,
+                         binary ? reinterpret_cast<uint32_t *>(ws + P.o_bits) : nullptr));
     return BN_OK;
 }
 

@@ -72,6 +72,18 @@ def test_local_scores_match_oracle(name):
         np.testing.assert_allclose(got[i], want, rtol=1e-12, atol=1e-10)
 
 
+@pytest.mark.parametrize("kind", ["bdeu", "k2"])
+def test_local_scores_binary_bitplanes(kind):
+    """All-binary data with d <= 4 is counted from bit planes; m not a
+    multiple of 32 leaves a ragged last word."""
+    ds = datagen.random_dag_dataset(11, 777, 2, 4, 1.0, seed=19)
+    got = bn.local_scores(ds.data, ds.arity, 4, score=kind, ess=2.5)
+    ref = O.local_scores(ds.data, ds.arity, 4, O.K2 if kind == "k2" else O.BDEU, 2.5)
+    masks = ranked_masks(10, 4)
+    for i in range(11):
+        np.testing.assert_allclose(got[i], ref[i, expand(masks, i)], rtol=1e-12, atol=1e-10)
+
+
 def test_local_scores_k2_mixed_arity():
     ds = datagen.random_dag_dataset(9, 333, [2, 3, 4, 2, 5, 3, 2, 2, 3], 3, 0.7, seed=8)
     got = bn.local_scores(ds.data, ds.arity, 3, score="k2")
