@@ -27,6 +27,9 @@
  * taken to depend on subset size only: log q(k), k = 0..n-1, and
  * log rho(k), k = 0..d.
  *
+ * A last section writes out the generic subset transforms of Def. 1 and
+ * Def. 2 (and their inverses) as plain sums over subsets or supersets.
+ *
  * Parity pins for this file live in the test suite: brute force over all
  * orders and over all DAGs, exact rational BDeu values, the m = 0 closed
  * form, the Gamma-free identity and the lattice invariants.
@@ -417,4 +420,79 @@ int or_edge_posteriors(int n, int m, const uint8_t *data, const uint8_t *arity, 
                                    nthreads);
     free(B);
     return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Generic subset sums (Def. 1 and Def. 2 written out as sums).         */
+/* ------------------------------------------------------------------ */
+
+/* Compensated (Neumaier) running sum, so the reference value is exact to a
+ * few units in the last place whatever the number of terms. */
+typedef struct { double s, c; } or_acc;
+static void acc_add(or_acc *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+/*
+ * One output of a subset transform of x (2^nbits values, x[S] for the subset
+ * S given by the index bits), straight from its definition:
+ *   kind 0 (upward zeta, Def. 1):   sum over S subset T with |S| <= d
+ *                                   (d < 0: no bound) of x[S]
+ *   kind 1 (downward zeta, Def. 2): sum over S superset T of x[S]
+ *   kind 2 (inverse of kind 0 without bound):
+ *                                   sum over S subset T of (-1)^|T-S| x[S]
+ *   kind 3 (inverse of kind 1):     sum over S superset T of (-1)^|S-T| x[S]
+ * absval != 0 sums |x[S]| instead, without signs (the scale of the
+ * rounding error).
+ * Subsets of T are enumerated as sub = (sub - 1) & T; supersets as the
+ * union of T with the subsets of its complement.
+ */
+static double subset_sum_one(int nbits, int kind, int d, const double *x, uint64_t T, int absval)
+{
+    const uint64_t full = (nbits == 64) ? ~0ull : ((1ull << nbits) - 1);
+    const int down = kind == 1 || kind == 3;
+    const int alt = kind == 2 || kind == 3;
+    const uint64_t free_bits = down ? (full & ~T) : T;
+    or_acc a = {0.0, 0.0};
+    uint64_t sub = free_bits;
+    for (;;) {
+        const uint64_t S = down ? (T | sub) : sub;
+        if (!(kind == 0 && d >= 0 && popc(S) > d)) {
+            double v = absval ? fabs(x[S]) : x[S];
+            if (alt && !absval && (popc(down ? (S & ~T) : (T & ~S)) & 1)) v = -v;
+            acc_add(&a, v);
+        }
+        if (sub == 0) break;
+        sub = (sub - 1) & free_bits;
+    }
+    return a.s + a.c;
+}
+
+/* Every output: out[T] for all 2^nbits subsets T (x and out distinct). */
+int or_subset_sums(int nbits, int kind, int d, const double *x, double *out, int absval,
+                   int nthreads)
+{
+    if (nbits < 0 || nbits > 30 || kind < 0 || kind > 3) return -1;
+    set_threads(nthreads);
+    const int64_t N = (int64_t)1 << nbits;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t T = 0; T < N; ++T) out[T] = subset_sum_one(nbits, kind, d, x, (uint64_t)T, absval);
+    return 0;
+}
+
+/* Selected outputs: out[k] for the subsets Ts[k], k < nT. The caller keeps
+ * the enumeration small (few members of T for kinds 0 and 2, few
+ * non-members for kinds 1 and 3). */
+int or_subset_sums_at(int nbits, int kind, int d, const double *x, const uint64_t *Ts,
+                      int64_t nT, double *out, int absval, int nthreads)
+{
+    if (nbits < 0 || nbits > 40 || kind < 0 || kind > 3) return -1;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < nT; ++k) out[k] = subset_sum_one(nbits, kind, d, x, Ts[k], absval);
+    return 0;
 }

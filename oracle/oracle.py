@@ -51,6 +51,12 @@ def _load():
                                            ctypes.c_int, ctypes.c_double, P, P, P, P,
                                            ctypes.c_int]
         lib.or_edge_posteriors.restype = ctypes.c_int
+        lib.or_subset_sums.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P,
+                                       ctypes.c_int, ctypes.c_int]
+        lib.or_subset_sums.restype = ctypes.c_int
+        lib.or_subset_sums_at.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P,
+                                          ctypes.c_int64, P, ctypes.c_int, ctypes.c_int]
+        lib.or_subset_sums_at.restype = ctypes.c_int
         lib.or_num_threads.argtypes = []
         lib.or_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -154,3 +160,42 @@ def full_log_beta(data: np.ndarray, arity, d: int, kind: int = BDEU, ess: float 
     ok = np.isfinite(s)
     s[ok] += lr[np.broadcast_to(pc, s.shape)[ok]]
     return s
+
+
+SUBSET_KINDS = {"zeta_up": 0, "zeta_down": 1, "mobius_up": 2, "mobius_down": 3}
+
+
+def subset_sums(x: np.ndarray, kind: str, d: int = -1, absval: bool = False,
+                nthreads: int = 0) -> np.ndarray:
+    """Every output of a subset transform of x[0 .. 2^nbits), by its definition.
+
+    zeta_up: t(T) = sum_{S subset T, |S| <= d} x(S) (Def. 1; d < 0: no bound);
+    zeta_down: t(T) = sum_{S superset T} x(S) (Def. 2); mobius_up / mobius_down:
+    the alternating sums that invert the untruncated forms. absval sums |x|.
+    Cost 3^nbits.
+    """
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    nbits = int(x.size).bit_length() - 1
+    assert x.size == 1 << nbits
+    out = np.empty_like(x)
+    rc = _load().or_subset_sums(nbits, SUBSET_KINDS[kind], int(d), _ptr(x), _ptr(out),
+                                int(absval), int(nthreads))
+    if rc:
+        raise RuntimeError(f"or_subset_sums failed ({rc})")
+    return out
+
+
+def subset_sums_at(x: np.ndarray, kind: str, Ts, d: int = -1, absval: bool = False,
+                   nthreads: int = 0) -> np.ndarray:
+    """The outputs t(T) for the subsets in Ts only (same definitions)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    nbits = int(x.size).bit_length() - 1
+    assert x.size == 1 << nbits
+    Ts = np.ascontiguousarray(Ts, dtype=np.uint64)
+    assert Ts.size == 0 or int(Ts.max()) < x.size
+    out = np.empty(Ts.size, dtype=np.float64)
+    rc = _load().or_subset_sums_at(nbits, SUBSET_KINDS[kind], int(d), _ptr(x), _ptr(Ts),
+                                   Ts.size, _ptr(out), int(absval), int(nthreads))
+    if rc:
+        raise RuntimeError(f"or_subset_sums_at failed ({rc})")
+    return out

@@ -125,3 +125,27 @@ def serving_stream(num: int = 512, seed: int = 4, rate_hz: float | None = None):
 def request_dataset(req: dict) -> Dataset:
     return random_dag_dataset(req["n"], req["m"], req["arity"], req["maxdeg"], req["a"],
                               req["seed"])
+
+
+def subset_values(nbits: int, seed: int, dist: str = "uniform") -> np.ndarray:
+    """2^nbits float64 values x[S] for the subset transforms.
+
+    dist: "uniform" U[0, 1) (nonnegative, like the products the method sums);
+    "signed" standard normal; "int" integers in [-1000, 1000] (every partial
+    sum is exact in FP64 up to 2^43 terms); "wide" 2^u with u ~ U[-600, 0]
+    (positive values spread over 180 decades, like probabilities);
+    "ones" all 1. rng = numpy.random.default_rng(seed).
+    """
+    size = 1 << nbits
+    rng = np.random.default_rng(seed)
+    if dist == "uniform":
+        return rng.random(size)
+    if dist == "signed":
+        return rng.standard_normal(size)
+    if dist == "int":
+        return rng.integers(-1000, 1001, size).astype(np.float64)
+    if dist == "wide":
+        return np.exp2(rng.uniform(-600.0, 0.0, size))
+    if dist == "ones":
+        return np.ones(size)
+    raise ValueError(f"unknown distribution {dist!r}")
