@@ -206,6 +206,37 @@ def serving(bn, datagen, num=512, check=8):
     return out
 
 
+def subset_bench(bn, torch, datagen, nbits=30, steps=5):
+    """Generic subset transforms in place on 2^nbits doubles (8 GiB at 30
+    bits): upward zeta, upward zeta with |S| <= 3, downward zeta, upward
+    Moebius. Each step restores the input (untimed) and times one transform
+    with events on the current stream. Algorithmic bytes: one read and one
+    write of every entry, 16 B per entry."""
+    base = torch.from_numpy(datagen.subset_values(nbits, 30, "uniform")).cuda()
+    xt = torch.empty_like(base)
+    nbytes = 16 * (1 << nbits)
+    out = dict(nbits=nbits, entries=1 << nbits, algorithmic_bytes=nbytes, steps=steps,
+               passes=1 + max(0, math.ceil((nbits - 12) / 6)), kinds={})
+    for kind, d in [("zeta_up", -1), ("zeta_up", 3), ("zeta_down", -1), ("mobius_up", -1)]:
+        tot = 0.0
+        for k in range(steps + 1):
+            xt.copy_(base)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            bn.subset_transform(xt, kind, d)
+            e1.record()
+            e1.synchronize()
+            if k > 0:     # the first call is a warmup
+                tot += e0.elapsed_time(e1)
+        ms = tot / steps
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out["kinds"][f"{kind}" + (f"_d{d}" if d >= 0 else "")] = dict(
+            ms=ms, GB_s=gbs, frac_of_one_pass=gbs / HBM_PEAK_GBS)
+    del base, xt
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(datagen, name, sample_n):
     from oracle import oracle as O
     ds, p = datagen.workload(name)
@@ -231,6 +262,9 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-subset", action="store_true")
+    ap.add_argument("--subset-only", action="store_true",
+                    help="only time the generic subset transforms (2^30 doubles) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES (counter calibration) and exit")
     ap.add_argument("--source-digest", action="store_true",
@@ -255,6 +289,9 @@ def main():
     from paper_1408_1664_amd import datagen
 
     torch.cuda.set_device(0)
+    if args.subset_only:
+        print(json.dumps({"subset_transform": subset_bench(bn, torch, datagen)}), flush=True)
+        return
     head = measure(bn, torch, datagen, args.workload, args.precision, args.steps, args.warmup)
     print(f"# {args.workload} {args.precision}: {head['ms_per_step']:.2f} ms/step, "
           f"{head['cells_per_s']:.3e} cells/s, phases {head['phases_ms']}", file=sys.stderr,
@@ -277,6 +314,12 @@ def main():
         serve = serving(bn, datagen)
         print(f"# serving: {serve['closed_loop']['solves_per_s']:.0f} solves/s saturated, "
               f"open-loop p50/p99 {[(round(o['p50_ms'], 2), round(o['p99_ms'], 2)) for o in serve['open_loop']]}",
+              file=sys.stderr, flush=True)
+    sub = None
+    if not args.no_subset:
+        sub = subset_bench(bn, torch, datagen)
+        print(f"# subset transforms 2^30: " + ", ".join(f"{k} {v['ms']:.2f} ms"
+                                                        for k, v in sub["kinds"].items()),
               file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
@@ -309,6 +352,7 @@ def main():
         "flushed": head["flushed"],
         "comparisons": comps,
         "serving": serve,
+        "subset_transform": sub,
     }
     print(json.dumps(out), flush=True)
 

@@ -217,6 +217,32 @@ bn_status bn_serve_poll(void *server, uint64_t ticket, double *post, bn_report *
 /* Stops the server; pending requests resolve to BN_ECANCELED. */
 bn_status bn_server_destroy(void *server);
 
+/*
+ * Subset transforms of a device array x of 2^nbits doubles, x[S] for the
+ * subset S given by the bits of the index, in place on the given stream
+ * (NULL: the default stream); returns without waiting.
+ *   BN_ZETA_UP      t(T) = sum_{S subset T, |S| <= d} x(S) for every T: the
+ *                   truncated upward zeta transform (Def. 1, Alg. 2); d < 0
+ *                   or d >= nbits: untruncated.
+ *   BN_ZETA_DOWN    t(T) = sum_{S superset T} x(S): the downward zeta
+ *                   transform (Def. 2, Alg. 3). Def. 2 requires the outputs
+ *                   with |T| <= d only; every output is computed.
+ *   BN_MOBIUS_UP    the inverse of the untruncated upward transform,
+ *                   t(T) = sum_{S subset T} (-1)^{|T - S|} x(S).
+ *   BN_MOBIUS_DOWN  the inverse of the downward transform.
+ * nbits in 1..32. BN_EINVAL: NULL array, nbits out of range, an unknown
+ * kind, or a truncated (0 <= d < nbits) Moebius transform. Summation is in
+ * FP64 in a fixed order (deterministic).
+ */
+typedef enum {
+    BN_ZETA_UP = 0,
+    BN_ZETA_DOWN = 1,
+    BN_MOBIUS_UP = 2,
+    BN_MOBIUS_DOWN = 3
+} bn_subset_kind;
+bn_status bn_subset_transform(double *dev_x, int32_t nbits, bn_subset_kind kind, int32_t d,
+                              void *hip_stream);
+
 const char *bn_status_string(bn_status s);
 
 #ifdef __cplusplus

@@ -30,7 +30,7 @@ EXPORTED = ["bn_num_parent_sets", "bn_local_scores", "bn_workspace_bytes",
             "bn_edge_posteriors", "bn_parent_set_posteriors", "bn_edge_posteriors_dev",
             "bn_timer_create",
             "bn_timer_destroy", "bn_timer_read", "bn_server_create", "bn_serve_submit",
-            "bn_serve_poll", "bn_server_destroy", "bn_status_string"]
+            "bn_serve_poll", "bn_server_destroy", "bn_subset_transform", "bn_status_string"]
 
 
 class BnError(RuntimeError):
@@ -105,6 +105,8 @@ def lib():
         L.bn_serve_poll.restype = ctypes.c_int
         L.bn_server_destroy.argtypes = [P]
         L.bn_server_destroy.restype = ctypes.c_int
+        L.bn_subset_transform.argtypes = [P, I32, ctypes.c_int, I32, P]
+        L.bn_subset_transform.restype = ctypes.c_int
         L.bn_status_string.argtypes = [ctypes.c_int]
         L.bn_status_string.restype = ctypes.c_char_p
         _lib = L
@@ -249,6 +251,28 @@ def edge_posteriors_dev(data_dev, arity, d, precision, ws, post_dev, diag_dev=No
                                         else ctypes.c_void_p(diag_dev.data_ptr()),
                                         None if timer is None else timer._h),
            "bn_edge_posteriors_dev")
+
+
+SUBSET_KINDS = {"zeta_up": 0, "zeta_down": 1, "mobius_up": 2, "mobius_down": 3}
+
+
+def subset_transform(x_dev, kind: str, d: int = -1, stream=None):
+    """In-place subset transform of a float64 device tensor of 2^nbits values
+    (bn_subset_transform): "zeta_up" (Def. 1, truncated to |S| <= d when
+    0 <= d < nbits), "zeta_down" (Def. 2), "mobius_up" / "mobius_down" (their
+    untruncated inverses). Enqueued on `stream` (torch.cuda.Stream, default the
+    current stream); returns without synchronising."""
+    import torch
+
+    assert x_dev.dtype == torch.float64 and x_dev.is_cuda and x_dev.is_contiguous()
+    size = x_dev.numel()
+    nbits = size.bit_length() - 1
+    if size < 2 or size != 1 << nbits:
+        raise ValueError("the array must hold 2^nbits values, nbits >= 1")
+    st = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+    _check(lib().bn_subset_transform(ctypes.c_void_p(x_dev.data_ptr()), nbits,
+                                     SUBSET_KINDS[kind], int(d), ctypes.c_void_p(st)),
+           "bn_subset_transform")
 
 
 class Server:

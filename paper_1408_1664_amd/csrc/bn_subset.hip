@@ -1,0 +1,172 @@
+// Subset transforms on device arrays of doubles (bn_subset_transform):
+// the truncated upward zeta transform (Def. 1), the downward zeta transform
+// (Def. 2; its truncation only limits which outputs are required) and the
+// inverses of the untruncated forms (Moebius), in place on 2^nbits values
+// x[S], S a bit mask.
+//
+// Layout of the work (nbits > 12):
+//   k_subset_tile      the low 12 bits of each 4096-entry tile, in registers
+//                      in three layouts with two LDS transposes (256 threads
+//                      x 16 entries); an upward truncated transform first
+//                      clears every input with more than d ones;
+//   k_subset_bits<B>   B <= 6 higher bits per pass, entirely in registers:
+//                      each thread holds the 2^B entries that differ in those
+//                      bits, consecutive threads consecutive low indices.
+// nbits <= 12: one workgroup in LDS (k_subset_small).
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "../../include/bn.h"
+
+namespace bnk {
+
+namespace {
+
+constexpr int kT = 256;
+
+__device__ inline uint32_t padx16(uint32_t x) { return x + (x >> 4); }
+
+// One zeta step over register bit q of 16 registers: up adds the entry
+// without the bit into the entry with it, down the other way; sign -1 gives
+// the Moebius step.
+template <bool UP>
+__device__ inline void reg_step(double *v, int q, double sign) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        if (UP && ((r >> q) & 1)) v[r] += sign * v[r ^ (1 << q)];
+        if (!UP && !((r >> q) & 1)) v[r] += sign * v[r | (1 << q)];
+    }
+}
+
+template <bool UP>
+__global__ void __launch_bounds__(kT)
+k_subset_tile(double *__restrict__ x, double sign, int trunc_d) {
+    __shared__ double gb[4096 + 256];
+    const int t = threadIdx.x;
+    const uint64_t base = (uint64_t)blockIdx.x << 12;
+    double v[16];
+    // layout A: y = t * 16 + r, bits 0..3 in registers
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = x[base + ((uint32_t)t << 4) + r];
+    if (trunc_d >= 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if (__popcll(base | ((uint32_t)t << 4) | r) > trunc_d) v[r] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) reg_step<UP>(v, q, sign);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) gb[padx16(((uint32_t)t << 4) | r)] = v[r];
+    __syncthreads();
+    // layout B: y = thi * 256 + r * 16 + tlo, bits 4..7
+    const uint32_t tlo = t & 15, thi = t >> 4;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = gb[padx16((thi << 8) | (r << 4) | tlo)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) reg_step<UP>(v, q, sign);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) gb[padx16((thi << 8) | (r << 4) | tlo)] = v[r];
+    __syncthreads();
+    // layout C: y = r * 256 + t, bits 8..11
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = gb[padx16((r << 8) | t)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) reg_step<UP>(v, q, sign);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[base + (r << 8) + t] = v[r];
+}
+
+// Bits j0 .. j0+B-1 (j0 >= 12). Thread column col = blockIdx * 256 + t
+// splits into lo (the low j0 bits) and hi (the bits above the group); its
+// registers hold the 2^B entries hi | r << j0 | lo. Consecutive threads take
+// consecutive lo, so every register load and store is one 2 KB run.
+template <bool UP, int B>
+__global__ void __launch_bounds__(kT)
+k_subset_bits(double *__restrict__ x, int j0, double sign) {
+    constexpr int NR = 1 << B;
+    const uint64_t col = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    const uint64_t lo = col & ((1ull << j0) - 1);
+    const uint64_t hi = (col >> j0) << (j0 + B);
+    double v[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v[r] = x[hi | ((uint64_t)r << j0) | lo];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (UP && ((r >> q) & 1)) v[r] += sign * v[r ^ (1 << q)];
+            if (!UP && !((r >> q) & 1)) v[r] += sign * v[r | (1 << q)];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) x[hi | ((uint64_t)r << j0) | lo] = v[r];
+}
+
+// nbits <= 12: the whole array in LDS, one step per bit.
+template <bool UP>
+__global__ void __launch_bounds__(kT)
+k_subset_small(double *__restrict__ x, int nbits, double sign, int trunc_d) {
+    __shared__ double s[4096];
+    const uint32_t N = 1u << nbits;
+    for (uint32_t i = threadIdx.x; i < N; i += kT)
+        s[i] = (trunc_d >= 0 && __popc(i) > trunc_d) ? 0.0 : x[i];
+    __syncthreads();
+    for (int j = 0; j < nbits; ++j) {
+        for (uint32_t i = threadIdx.x; i < N; i += kT) {
+            if (UP && ((i >> j) & 1)) s[i] += sign * s[i ^ (1u << j)];
+            if (!UP && !((i >> j) & 1)) s[i] += sign * s[i | (1u << j)];
+        }
+        __syncthreads();
+    }
+    for (uint32_t i = threadIdx.x; i < N; i += kT) x[i] = s[i];
+}
+
+template <bool UP>
+hipError_t run(double *x, int nbits, double sign, int trunc_d, hipStream_t st) {
+    if (nbits <= 12) {
+        hipLaunchKernelGGL(k_subset_small<UP>, dim3(1), dim3(kT), 0, st, x, nbits, sign, trunc_d);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_subset_tile<UP>, dim3((unsigned)(1ull << (nbits - 12))), dim3(kT), 0, st,
+                       x, sign, trunc_d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int j0 = 12; j0 < nbits; j0 += 6) {
+        const int B = nbits - j0 < 6 ? nbits - j0 : 6;
+        // 2^(nbits - B) columns, 256 per workgroup (nbits - B >= 12)
+        const dim3 grid((unsigned)(1ull << (nbits - B - 8)));
+        switch (B) {
+            case 1: hipLaunchKernelGGL((k_subset_bits<UP, 1>), grid, dim3(kT), 0, st, x, j0, sign); break;
+            case 2: hipLaunchKernelGGL((k_subset_bits<UP, 2>), grid, dim3(kT), 0, st, x, j0, sign); break;
+            case 3: hipLaunchKernelGGL((k_subset_bits<UP, 3>), grid, dim3(kT), 0, st, x, j0, sign); break;
+            case 4: hipLaunchKernelGGL((k_subset_bits<UP, 4>), grid, dim3(kT), 0, st, x, j0, sign); break;
+            case 5: hipLaunchKernelGGL((k_subset_bits<UP, 5>), grid, dim3(kT), 0, st, x, j0, sign); break;
+            default: hipLaunchKernelGGL((k_subset_bits<UP, 6>), grid, dim3(kT), 0, st, x, j0, sign); break;
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+}  // namespace bnk
+
+extern "C" bn_status bn_subset_transform(double *dev_x, int32_t nbits, bn_subset_kind kind,
+                                         int32_t d, void *hip_stream) {
+    if (!dev_x || nbits < 1 || nbits > 32) return BN_EINVAL;
+    if (kind != BN_ZETA_UP && kind != BN_ZETA_DOWN && kind != BN_MOBIUS_UP &&
+        kind != BN_MOBIUS_DOWN)
+        return BN_EINVAL;
+    const bool mobius = kind == BN_MOBIUS_UP || kind == BN_MOBIUS_DOWN;
+    if (mobius && d >= 0 && d < nbits) return BN_EINVAL;   // only the untruncated forms invert
+    const int trunc = (kind == BN_ZETA_UP && d >= 0 && d < nbits) ? d : -1;
+    const double sign = mobius ? -1.0 : 1.0;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    const bool up = kind == BN_ZETA_UP || kind == BN_MOBIUS_UP;
+    const hipError_t e = up ? bnk::run<true>(dev_x, nbits, sign, trunc, st)
+                            : bnk::run<false>(dev_x, nbits, sign, trunc, st);
+    return e == hipSuccess ? BN_OK : BN_EDEVICE;
+}

@@ -117,3 +117,15 @@ def test_parent_set_posteriors_needs_an_output():
     h = bn._ProblemHold(data, arity, 2, "bdeu", 1.0, None, None)
     st = bn.lib().bn_parent_set_posteriors(h.ref(), 1, None, None, None)
     assert st == bn.BN_EINVAL
+
+
+def test_subset_transform_rejects_bad_arguments():
+    import ctypes
+    L = bn.lib()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails the checks
+    assert L.bn_subset_transform(None, 10, 0, -1, None) == bn.BN_EINVAL
+    assert L.bn_subset_transform(fake, 0, 0, -1, None) == bn.BN_EINVAL
+    assert L.bn_subset_transform(fake, 33, 0, -1, None) == bn.BN_EINVAL
+    assert L.bn_subset_transform(fake, 10, 4, -1, None) == bn.BN_EINVAL
+    assert L.bn_subset_transform(fake, 10, 2, 3, None) == bn.BN_EINVAL   # truncated inverse
+    assert L.bn_subset_transform(fake, 10, 3, 0, None) == bn.BN_EINVAL

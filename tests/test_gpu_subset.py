@@ -1,0 +1,150 @@
+"""GPU parity of the generic subset transforms (bn_subset_transform) against
+the oracle's subset sums.
+
+Tolerance. The kernels build each output through nbits rounds of pairwise
+additions, so the rounding error of an output is at most about
+nbits * 2^-53 times the sum of the absolute values of its terms; the oracle's
+compensated sums are exact to a few units in the last place. The bound checked
+is (nbits + 2) * 2^-53 * sum |terms|, the latter from the oracle (absval).
+Integer inputs are bit-exact: every partial sum is an integer below 2^53.
+
+Sizes: every output up to nbits = 16 (the oracle costs 3^nbits); sampled
+outputs above that, up to the 2^30-entry full size, with samples drawn so the
+oracle enumerates at most 2^17 terms per output (plus the full set under a
+degree bound).
+"""
+import numpy as np
+import pytest
+
+import paper_1408_1664_amd as bn
+from oracle import oracle as O
+from paper_1408_1664_amd import datagen
+
+pytestmark = pytest.mark.gpu
+KINDS = ["zeta_up", "zeta_down", "mobius_up", "mobius_down"]
+U = 2.0 ** -53
+
+
+def _gpu(x, kind, d=-1, stream=None):
+    import torch
+    xt = torch.from_numpy(x).cuda()
+    bn.subset_transform(xt, kind, d, stream=stream)
+    torch.cuda.synchronize()
+    return xt.cpu().numpy()
+
+
+def _check(got, want, absum, nbits, what):
+    err = np.abs(got - want)
+    bound = (nbits + 2) * U * absum
+    bad = np.flatnonzero(err > bound)
+    assert bad.size == 0, (f"{what}: {bad.size} outputs out of bound, first at {bad[0]}: "
+                           f"{got[bad[0]]!r} vs {want[bad[0]]!r} (bound {bound[bad[0]]:.3e})")
+
+
+def _cases(nbits):
+    out = [(k, -1) for k in KINDS]
+    out += [("zeta_up", d) for d in sorted({0, 2, nbits - 1, nbits}) if d >= 0]
+    return out
+
+
+@pytest.mark.parametrize("nbits", [1, 2, 5, 8, 12, 13, 14, 15, 16])
+@pytest.mark.parametrize("dist", ["uniform", "signed", "wide"])
+def test_every_output(nbits, dist):
+    x = datagen.subset_values(nbits, 100 + nbits, dist)
+    for kind, d in _cases(nbits):
+        print(f"subset nbits={nbits} dist={dist} kind={kind} d={d}", flush=True)
+        got = _gpu(x, kind, d)
+        want = O.subset_sums(x, kind, d)
+        absum = O.subset_sums(x, kind, d, absval=True)
+        _check(got, want, absum, nbits, f"{kind} d={d}")
+
+
+@pytest.mark.parametrize("nbits", [3, 12, 13, 16, 17, 18, 19])
+def test_integer_inputs_bit_exact_and_round_trip(nbits):
+    import torch
+    x = datagen.subset_values(nbits, 7 + nbits, "int")
+    small = nbits <= 16
+    for kind, d in _cases(nbits):
+        print(f"subset int nbits={nbits} kind={kind} d={d}", flush=True)
+        got = _gpu(x, kind, d)
+        if small:
+            np.testing.assert_array_equal(got, O.subset_sums(x, kind, d))
+        else:
+            Ts = _samples(nbits, kind, d, 512, seed=nbits)
+            np.testing.assert_array_equal(got[Ts.astype(np.int64)],
+                                          O.subset_sums_at(x, kind, Ts, d))
+    for fwd, inv in [("zeta_up", "mobius_up"), ("zeta_down", "mobius_down")]:
+        xt = torch.from_numpy(x).cuda()
+        bn.subset_transform(xt, fwd)
+        bn.subset_transform(xt, inv)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(xt.cpu().numpy(), x)
+
+
+def _samples(nbits, kind, d, count, seed, maxfree=17):
+    """Random subsets T whose oracle enumeration stays below 2^maxfree terms:
+    at most maxfree members (upward kinds) or non-members (downward kinds);
+    plus the empty and full sets where they are cheap."""
+    rng = np.random.default_rng(seed)
+    Ts = []
+    for _ in range(count):
+        k = int(rng.integers(0, min(maxfree, nbits) + 1))
+        bits = rng.choice(nbits, k, replace=False)
+        T = int(sum(1 << int(b) for b in bits))
+        if "down" in kind:
+            T = ((1 << nbits) - 1) ^ T
+        Ts.append(T)
+    Ts += [0, (1 << nbits) - 1] if nbits <= maxfree else []
+    if nbits > maxfree:
+        Ts.append(0 if kind.endswith("up") else (1 << nbits) - 1)
+    return np.array(Ts, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("nbits", [17, 18, 19, 20, 24, 25])
+def test_sampled_outputs(nbits):
+    x = datagen.subset_values(nbits, 200 + nbits, "uniform")
+    for kind, d in _cases(nbits):
+        print(f"subset sampled nbits={nbits} kind={kind} d={d}", flush=True)
+        got = _gpu(x, kind, d)
+        Ts = _samples(nbits, kind, d, 1024, seed=nbits * 7 + len(kind))
+        want = O.subset_sums_at(x, kind, Ts, d)
+        absum = O.subset_sums_at(x, kind, Ts, d, absval=True)
+        _check(got[Ts.astype(np.int64)], want, absum, nbits, f"{kind} d={d}")
+
+
+def test_side_stream_and_degree_zero():
+    import torch
+    nbits = 20
+    x = datagen.subset_values(nbits, 5, "uniform")
+    s = torch.cuda.Stream()
+    xt = torch.from_numpy(x).cuda()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bn.subset_transform(xt, "zeta_up", 0, stream=s)
+    s.synchronize()
+    # d = 0: every output is x(empty)
+    np.testing.assert_array_equal(xt.cpu().numpy(), np.full(1 << nbits, x[0]))
+
+
+def test_full_size_2_30_sampled():
+    """2^30 entries (8 GiB): the size the transform is timed at."""
+    import torch
+    nbits = 30
+    print("subset full size: drawing 2^30 values", flush=True)
+    x = datagen.subset_values(nbits, 30, "uniform")
+    base = torch.from_numpy(x).cuda()
+    for kind, d in [("zeta_up", -1), ("zeta_up", 3), ("zeta_down", -1), ("mobius_up", -1)]:
+        print(f"subset full size kind={kind} d={d}", flush=True)
+        xt = base.clone()
+        bn.subset_transform(xt, kind, d)
+        Ts = _samples(nbits, kind, d, 512, seed=len(kind) + d, maxfree=16)
+        if d >= 0:
+            Ts = np.append(Ts, np.uint64((1 << nbits) - 1))   # 2^30 candidates, few kept
+        idx = torch.from_numpy(Ts.astype(np.int64)).cuda()
+        got = xt[idx].cpu().numpy()
+        del xt
+        want = O.subset_sums_at(x, kind, Ts, d)
+        absum = O.subset_sums_at(x, kind, Ts, d, absval=True)
+        _check(got, want, absum, nbits, f"{kind} d={d}")
+    del base
+    torch.cuda.empty_cache()
