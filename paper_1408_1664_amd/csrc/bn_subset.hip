@@ -4,14 +4,17 @@
 // inverses of the untruncated forms (Moebius), in place on 2^nbits values
 // x[S], S a bit mask.
 //
-// Layout of the work (nbits > 12):
+// Layout of the work (nbits > 12): three passes over the array at 30 bits,
+// each one read and one write of every entry.
 //   k_subset_tile      the low 12 bits of each 4096-entry tile, in registers
 //                      in three layouts with two LDS transposes (256 threads
 //                      x 16 entries); an upward truncated transform first
 //                      clears every input with more than d ones;
-//   k_subset_bits<B>   B <= 6 higher bits per pass, entirely in registers:
-//                      each thread holds the 2^B entries that differ in those
-//                      bits, consecutive threads consecutive low indices.
+//   k_subset_group     the remaining bits in passes of at most 9 (split
+//                      evenly), 32 columns x 2^B patterns per workgroup, two
+//                      register layouts joined through LDS;
+//   k_subset_bits<B>   a remainder of B <= 4 bits (nbits 13..16), entirely
+//                      in registers.
 // nbits <= 12: one workgroup in LDS (k_subset_small).
 #include <hip/hip_runtime.h>
 
@@ -78,10 +81,10 @@ k_subset_tile(double *__restrict__ x, double sign, int trunc_d) {
     for (int r = 0; r < 16; ++r) x[base + (r << 8) + t] = v[r];
 }
 
-// Bits j0 .. j0+B-1 (j0 >= 12). Thread column col = blockIdx * 256 + t
-// splits into lo (the low j0 bits) and hi (the bits above the group); its
-// registers hold the 2^B entries hi | r << j0 | lo. Consecutive threads take
-// consecutive lo, so every register load and store is one 2 KB run.
+// Bits j0 .. j0+B-1 (j0 >= 12, B <= 4). Thread column col = blockIdx * 256
+// + t splits into lo (the low j0 bits) and hi (the bits above the group);
+// its registers hold the 2^B entries hi | r << j0 | lo. Consecutive threads
+// take consecutive lo, so every register load and store is one 2 KB run.
 template <bool UP, int B>
 __global__ void __launch_bounds__(kT)
 k_subset_bits(double *__restrict__ x, int j0, double sign) {
@@ -102,6 +105,90 @@ k_subset_bits(double *__restrict__ x, int j0, double sign) {
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) x[hi | ((uint64_t)r << j0) | lo] = v[r];
+}
+
+// Bits j0 .. j0+B-1 (j0 >= 12, 5 <= B <= 9) over W = 2^LW consecutive low
+// indices per workgroup, 32 entries per thread, NT = 2^(B+LW-5) threads.
+// Entry (column c, pattern p) is x[hi | p << j0 | lo0 + c]. First layout:
+// the registers hold pattern bits 0..4, the thread index the column and
+// pattern bits 5..B-1 (TP = B-5 bits). Second layout: the registers hold
+// pattern bits TP..TP+4, the thread index the column and pattern bits
+// 0..TP-1. Bit 4 is a register bit in both, so the exchange runs in two
+// rounds (bit 4 = 0, then 1) through half the entries' worth of LDS. Global
+// accesses are runs of W doubles.
+template <bool UP, int B, int LW>
+__global__ void __launch_bounds__(1 << (B + LW - 5))
+k_subset_group(double *__restrict__ x, int j0, double sign) {
+    constexpr int W = 1 << LW;
+    constexpr int TP = B - 5;
+    constexpr int NH = (1 << (B - 1)) * W;             // entries per exchange round
+    constexpr int NPAD = (1 << (B - 1)) / 16 * 16;
+    __shared__ double sb[TP > 0 ? NH + NPAD : 1];
+    const uint32_t t = threadIdx.x;
+    const uint32_t c = t & (W - 1);
+    const uint32_t tp = t >> LW;
+    const uint64_t w = blockIdx.x;
+    const int cb = j0 - LW;                            // bits of the column-chunk index
+    const uint64_t lo = ((w & ((1ull << cb) - 1)) << LW) | c;
+    const uint64_t hi = (w >> cb) << (j0 + B);
+    double *xb = x + (hi | lo);
+    double v[32];
+#pragma unroll
+    for (int r = 0; r < 32; ++r) v[r] = xb[(uint64_t)((tp << 5) | r) << j0];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+#pragma unroll
+        for (int r = 0; r < 32; ++r) {
+            if (UP && ((r >> q) & 1)) v[r] += sign * v[r ^ (1 << q)];
+            if (!UP && !((r >> q) & 1)) v[r] += sign * v[r | (1 << q)];
+        }
+    }
+    if constexpr (TP > 0) {
+        // LDS slot of pattern p (bit 4 dropped) and column col
+        auto at = [](uint32_t p, uint32_t col) {
+            const uint32_t q = (p & 15) | ((p >> 5) << 4);
+            return q * W + col + (q >> 4) * 16;
+        };
+        double u[32];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h) __syncthreads();
+#pragma unroll
+            for (int r = 16 * h; r < 16 * h + 16; ++r) sb[at((tp << 5) | r, c)] = v[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 32; ++r) {
+                const uint32_t p = ((uint32_t)r << TP) | tp;
+                if (((p >> 4) & 1) == (uint32_t)h) u[r] = sb[at(p, c)];
+            }
+        }
+        // register bit q is pattern bit TP + q; bits 5..B-1 remain
+#pragma unroll
+        for (int q = 5 - TP; q < 5; ++q) {
+#pragma unroll
+            for (int r = 0; r < 32; ++r) {
+                if (UP && ((r >> q) & 1)) u[r] += sign * u[r ^ (1 << q)];
+                if (!UP && !((r >> q) & 1)) u[r] += sign * u[r | (1 << q)];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 32; ++r) xb[(uint64_t)(((uint32_t)r << TP) | tp) << j0] = u[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < 32; ++r) xb[(uint64_t)((tp << 5) | r) << j0] = v[r];
+    }
+}
+
+template <bool UP, int LW>
+void launch_group(int B, int nbits, double *x, int j0, double sign, hipStream_t st) {
+    const dim3 grid((unsigned)(1ull << (nbits - B - LW)));
+    switch (B) {
+        case 5: hipLaunchKernelGGL((k_subset_group<UP, 5, LW>), grid, dim3(1 << LW), 0, st, x, j0, sign); break;
+        case 6: hipLaunchKernelGGL((k_subset_group<UP, 6, LW>), grid, dim3(1 << (1 + LW)), 0, st, x, j0, sign); break;
+        case 7: hipLaunchKernelGGL((k_subset_group<UP, 7, LW>), grid, dim3(1 << (2 + LW)), 0, st, x, j0, sign); break;
+        case 8: hipLaunchKernelGGL((k_subset_group<UP, 8, LW>), grid, dim3(1 << (3 + LW)), 0, st, x, j0, sign); break;
+        default: hipLaunchKernelGGL((k_subset_group<UP, 9, LW>), grid, dim3(1 << (4 + LW)), 0, st, x, j0, sign); break;
+    }
 }
 
 // nbits <= 12: the whole array in LDS, one step per bit.
@@ -133,20 +220,25 @@ hipError_t run(double *x, int nbits, double sign, int trunc_d, hipStream_t st) {
                        x, sign, trunc_d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    for (int j0 = 12; j0 < nbits; j0 += 6) {
-        const int B = nbits - j0 < 6 ? nbits - j0 : 6;
-        // 2^(nbits - B) columns, 256 per workgroup (nbits - B >= 12)
-        const dim3 grid((unsigned)(1ull << (nbits - B - 8)));
-        switch (B) {
-            case 1: hipLaunchKernelGGL((k_subset_bits<UP, 1>), grid, dim3(kT), 0, st, x, j0, sign); break;
-            case 2: hipLaunchKernelGGL((k_subset_bits<UP, 2>), grid, dim3(kT), 0, st, x, j0, sign); break;
-            case 3: hipLaunchKernelGGL((k_subset_bits<UP, 3>), grid, dim3(kT), 0, st, x, j0, sign); break;
-            case 4: hipLaunchKernelGGL((k_subset_bits<UP, 4>), grid, dim3(kT), 0, st, x, j0, sign); break;
-            case 5: hipLaunchKernelGGL((k_subset_bits<UP, 5>), grid, dim3(kT), 0, st, x, j0, sign); break;
-            default: hipLaunchKernelGGL((k_subset_bits<UP, 6>), grid, dim3(kT), 0, st, x, j0, sign); break;
+    const int rem = nbits - 12;
+    const int npass = (rem + 8) / 9;          // at most 9 bits per pass, split evenly
+    for (int i = 0, j0 = 12; i < npass; ++i) {
+        const int B = rem / npass + (i < rem % npass ? 1 : 0);
+        if (B >= 5) {
+            launch_group<UP, 5>(B, nbits, x, j0, sign, st);
+        } else {
+            // 2^(nbits - B) columns, 256 per workgroup (nbits - B >= 12)
+            const dim3 grid((unsigned)(1ull << (nbits - B - 8)));
+            switch (B) {
+                case 1: hipLaunchKernelGGL((k_subset_bits<UP, 1>), grid, dim3(kT), 0, st, x, j0, sign); break;
+                case 2: hipLaunchKernelGGL((k_subset_bits<UP, 2>), grid, dim3(kT), 0, st, x, j0, sign); break;
+                case 3: hipLaunchKernelGGL((k_subset_bits<UP, 3>), grid, dim3(kT), 0, st, x, j0, sign); break;
+                default: hipLaunchKernelGGL((k_subset_bits<UP, 4>), grid, dim3(kT), 0, st, x, j0, sign); break;
+            }
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+        j0 += B;
     }
     return hipSuccess;
 }
