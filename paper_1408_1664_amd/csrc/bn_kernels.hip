@@ -541,9 +541,10 @@ __host__ __device__ constexpr uint32_t colex5(uint32_t r) {
 
 // Seeds of the linear alpha tiles, in a kernel of their own (the gather of
 // k_alpha's first step, at high occupancy). For tile (i, H) and every G_L
-// over the 13 tile bits with |G_L| <= d,
+// over the 13 tile bits with |G_L| < d,
 //   Zs[(i, H)][rank(G_L)] = sum_{G_H subset H, |G_H| <= d - |G_L|} betal_i(G_H + G_L),
-// rank = size, then colex order. For one G_H the G_L of one size s give a
+// rank = size, then colex order. A seed with |G_L| = d is betal_i(G_L)
+// itself, the same for every H: k_alpha_lin reads those from betal. For one G_H the G_L of one size s give a
 // contiguous run of ranks of G_H + G_L, so consecutive lanes take
 // consecutive G_L (coalesced loads) and groups of lanes split the G_H;
 // their partial sums meet in LDS in a fixed order.
@@ -597,7 +598,7 @@ k_alpha_seeds(int n, int d, uint32_t K, uint32_t KS, int use_prk, Tables tb,
     __syncthreads();
     const double *bi = betal + (size_t)i * K;
     double *out = Zs + (size_t)blockIdx.x * KS;
-    for (int s = 0; s <= d && s <= bA; ++s) {
+    for (int s = 0; s < d && s <= bA; ++s) {
         const uint32_t nseed = C(bn, bA, s);
         const uint32_t items = Kcount(bn, h, d - s);
         const uint32_t seedoff = Kcount(bn, bA, s - 1);
@@ -736,6 +737,7 @@ __host__ __device__ constexpr uint32_t colex4(uint32_t r) {
 // One 12-bit half of a linear alpha tile (see k_alpha_lin).
 template <class P, int hb>
 __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__ zs,
+                                               const double *__restrict__ zd,
                                                const typename P::V *sq, const uint16_t *cb,
                                                const uint32_t *k13, uint32_t *tlo_,
                                                uint32_t *thi_, uint32_t pt, int h,
@@ -767,15 +769,16 @@ __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__
             off[m] = k13[min(kp + m, 14)];
             offu[m] = k13[min(kp + m + 1, 14)];
         }
-        // every load is issued (clamped to a valid index) before any is used
+        // every load is issued (clamped to a valid index of zd) before any is
+        // used; seeds of size d come from zd, smaller ones from zs
         double u[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const int m = __builtin_popcount(r);
             const uint32_t il = (kp + m <= d) ? off[m] + colex4(r) + cpt[m] : 0u;
             const uint32_t iu = (hb && kp + m + 1 <= d) ? offu[m] + colex4(r) + cup[m] : 0u;
-            v[r] = zs[il];
-            u[r] = zs[iu];
+            v[r] = (kp + m < d ? zs : zd)[il];
+            u[r] = (kp + m + 1 < d ? zs : zd)[iu];
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -873,6 +876,7 @@ __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__
 template <class P>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_alpha_lin(int n, int d, uint32_t KS, int force_fb, const double *__restrict__ Zs,
+            const double *__restrict__ betal, uint32_t K, uint32_t offd,
             const typename P::Anchor *__restrict__ anc, const int *__restrict__ linok,
             const typename P::V *__restrict__ qt, typename P::Store alpha,
             unsigned long long *cnt, uint32_t *fb) {
@@ -917,10 +921,13 @@ k_alpha_lin(int n, int d, uint32_t KS, int force_fb, const double *__restrict__ 
     __syncthreads();
     const int h = __popc(H);
     const double *zs = Zs + (size_t)blockIdx.x * KS;
+    // size-d seeds: betal_i(G_L) at rank offd + colex(G_L), offd = K(N, d - 1);
+    // indexed like zs (k13[d] + colex), so the base is shifted by k13[d]
+    const double *zd = betal + (size_t)i * K + offd - k13[min(d, 14)];
     const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
     const uint32_t pt = ord8[t];
-    alpha_lin_half<P, 0>(d, zs, sq, cb, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
-    alpha_lin_half<P, 1>(d, zs, sq, cb, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
+    alpha_lin_half<P, 0>(d, zs, zd, sq, cb, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
+    alpha_lin_half<P, 1>(d, zs, zd, sq, cb, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
 
 }
 
@@ -2248,6 +2255,16 @@ hipError_t launch_scores(int n, int m, const uint8_t *data, const uint8_t *arity
     return hipSuccess;
 }
 
+// sum_{k <= t} C(w, k) on the host (0 for t < 0)
+static uint32_t host_kcount(int w, int t) {
+    uint64_t sum = 0, c = 1;
+    for (int k = 0; k <= t && k <= w; ++k) {
+        sum += c;
+        c = c * (uint64_t)(w - k) / (uint64_t)(k + 1);
+    }
+    return (uint32_t)sum;
+}
+
 template <class P>
 hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
                           const typename P::Store &L, const typename P::Store &R,
@@ -2293,7 +2310,8 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
             rec(8);
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_lin<P>), dim3(nblkA), dim3(kThreads), smL,
                                st, n, d, a.KS, a.lin_mode == 2 ? 1 : 0, (const double *)a.Zs,
-                               (const A *)a.anc, (const int *)a.linok, (const V *)qt, alpha,
+                               (const double *)a.betal, a.K,
+                               host_kcount(N, d - 1), (const A *)a.anc, (const int *)a.linok, (const V *)qt, alpha,
                                a.cnt, a.fbA);
             BN_CHECK_LAUNCH();
             rec(9);

@@ -214,7 +214,7 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     // Linear alpha tiles keep their seeds (K(13, d) doubles per tile) in the
     // workspace when those take at most 16 GiB; otherwise alpha runs in the
     // number system proper.
-    P.KS = P.bA == 13 ? (uint32_t)kcount_u64(13, d) : 0;
+    P.KS = (P.bA == 13 && d > 0) ? (uint32_t)kcount_u64(13, d - 1) : 0;   // seeds of size < d
     const uint64_t zs_bytes = P.bA == 13 ? ((uint64_t)n << (N - 13)) * P.KS * 8 : 0;
     P.alpha_lin = P.lin_mode != 0 && P.bA == 13 && zs_bytes <= (16ull << 30);
     P.o_Zs = P.alpha_lin ? take(zs_bytes) : 0;
