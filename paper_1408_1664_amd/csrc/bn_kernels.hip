@@ -738,7 +738,8 @@ __host__ __device__ constexpr uint32_t colex4(uint32_t r) {
 template <class P, int hb>
 __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__ zs,
                                                const double *__restrict__ zd,
-                                               const typename P::V *sq, const uint16_t *cb,
+                                               const typename P::V *sq, const uint32_t *cpt,
+                                               const uint32_t *cup,
                                                const uint32_t *k13, uint32_t *tlo_,
                                                uint32_t *thi_, uint32_t pt, int h,
                                                uint64_t base, typename P::Anchor T,
@@ -755,17 +756,9 @@ __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__
     //      from its own seeds plus the lower half's (the zeta step over
     //      tile bit 12 commutes with the others).
     if (__any(kp <= d)) {
-        // colex contribution of pt's bits (tile bits 4..11), and of bit 12
-        // in the upper half, by the number m of set bits below them
-        uint32_t cpt[5], cup[5], off[5], offu[5];
+        uint32_t off[5], offu[5];
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
-            uint32_t c = 0;
-            int j = m;
-            for (int p = 0; p < 8; ++p)
-                if ((pt >> p) & 1) c += (4 + p >= ++j) ? cb[(4 + p) * 14 + j] : 0u;
-            cpt[m] = c;
-            cup[m] = c + ((12 >= j + 1) ? cb[12 * 14 + j + 1] : 0u);
             off[m] = k13[min(kp + m, 14)];
             offu[m] = k13[min(kp + m + 1, 14)];
         }
@@ -826,23 +819,41 @@ __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__
         float *fp = alpha.f + ub;
         uint8_t *bytes = reinterpret_cast<uint8_t *>(tlo_);
         uint32_t nsat = 0, nfl = 0, bq[NR];
+        double qf[5];
+        int qb[5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            qf[m] = (double)qr[m].f;
+            qb[m] = ((T + qr[m].e) >> 6) + kX32Bias;
+        }
+        // fast path: every entry positive with its byte in 1..255
+        float fq[NR];
+        bool ok = true;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const X32 q = qr[__builtin_popcount(r)];
-            const double z = v[r] * (double)q.f;
+            const int m = __builtin_popcount(r);
+            const double z = v[r] * qf[m];
             int k;
-            float f = PolX32::lin_encode(z, &k);
-            int b = ((T + q.e) >> 6) + k + kX32Bias;
-            const bool zero = !(z > 0.0);
-            const bool fl = !zero && b < 1;
-            const bool sat = !zero && b > 255;
-            nfl += fl ? 1u : 0u;
-            nsat += sat ? 1u : 0u;
-            f = (zero || fl) ? 0.0f : (sat ? 4.0e9f : f);
-            b = (zero || fl) ? 0 : (sat ? 255 : b);
-            fp[(uint32_t)(r * kThreads + t)] = f;
-            bq[r] = (uint32_t)b;
+            fq[r] = PolX32::lin_encode(z, &k);
+            bq[r] = (uint32_t)(qb[m] + k);
+            ok = ok && z > 0.0 && bq[r] - 1u < 255u;
         }
+        if (!ok) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const double z = v[r] * qf[__builtin_popcount(r)];
+                const int b = (int)bq[r];
+                const bool zero = !(z > 0.0);
+                const bool fl = !zero && b < 1;
+                const bool sat = !zero && b > 255;
+                nfl += fl ? 1u : 0u;
+                nsat += sat ? 1u : 0u;
+                fq[r] = (zero || fl) ? 0.0f : (sat ? 4.0e9f : fq[r]);
+                bq[r] = (zero || fl) ? 0u : (sat ? 255u : (uint32_t)b);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) fp[(uint32_t)(r * kThreads + t)] = fq[r];
         __syncthreads();                      // every layout-C read of the planes is done
 #pragma unroll
         for (int r = 0; r < NR; ++r) bytes[r * kThreads + t] = (uint8_t)bq[r];
@@ -926,8 +937,25 @@ k_alpha_lin(int n, int d, uint32_t KS, int force_fb, const double *__restrict__ 
     const double *zd = betal + (size_t)i * K + offd - k13[min(d, 14)];
     const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
     const uint32_t pt = ord8[t];
-    alpha_lin_half<P, 0>(d, zs, zd, sq, cb, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
-    alpha_lin_half<P, 1>(d, zs, zd, sq, cb, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
+    // colex contribution of pt's bits (tile bits 4..11), and of bit 12 in the
+    // upper half, by the number m of set bits below them (both halves)
+    uint32_t cpt[5], cup[5];
+    if (__popc(pt) <= d) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            uint32_t c = 0;
+            int j = m;
+            for (int p = 0; p < 8; ++p)
+                if ((pt >> p) & 1) c += (4 + p >= ++j) ? cb[(4 + p) * 14 + j] : 0u;
+            cpt[m] = c;
+            cup[m] = c + ((12 >= j + 1) ? cb[12 * 14 + j + 1] : 0u);
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) cpt[m] = cup[m] = 0;
+    }
+    alpha_lin_half<P, 0>(d, zs, zd, sq, cpt, cup, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
+    alpha_lin_half<P, 1>(d, zs, zd, sq, cpt, cup, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
 
 }
 
