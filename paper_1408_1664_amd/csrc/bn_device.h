@@ -56,6 +56,7 @@ struct PolLog {
         o[2] = r.b.x;
         o[3] = r.b.y;
     }
+    __device__ static inline void decode4_nz(const Raw4 &r, V *o) { decode4(r, o); }
     __device__ static inline V from_log(double x) { return x; }
     __device__ static inline double to_log(V v) { return v; }
     // log(a / b) in FP64, a, b > 0
@@ -209,6 +210,15 @@ struct PolX32 {
         o[1] = decode(r.f.y, (r.b >> 8) & 0xff);
         o[2] = decode(r.f.z, (r.b >> 16) & 0xff);
         o[3] = decode(r.f.w, r.b >> 24);
+    }
+    // decode4 without the zero test, for factors of a product only: a stored
+    // zero has significand 0, so the product is an exact zero whatever the
+    // exponent carried with it.
+    __device__ static inline void decode4_nz(const Raw4 &r, V *o) {
+        o[0] = X32{r.f.x, (int)((r.b & 0xff) - kX32Bias) << 6};
+        o[1] = X32{r.f.y, (int)(((r.b >> 8) & 0xff) - kX32Bias) << 6};
+        o[2] = X32{r.f.z, (int)(((r.b >> 16) & 0xff) - kX32Bias) << 6};
+        o[3] = X32{r.f.w, (int)((r.b >> 24) - kX32Bias) << 6};
     }
     // Encode one value: returns the byte, writes the significand to *f.
     // cnt[0] counts saturations, cnt[1] flushes of nonzero values.

@@ -1021,7 +1021,7 @@ __device__ inline void stage_alpha(const typename P::Store &alpha, uint64_t NN, 
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t e = e0 + 4 * kThreads * u;
-                if (e < total) P::decode4(raw[u], la + e);
+                if (e < total) P::decode4_nz(raw[u], la + e);   // product factors only
             }
         }
     } else {
@@ -1051,8 +1051,8 @@ __device__ inline void cross_terms(const typename P::Store &alpha, const typenam
         for (int u = 0; u < B; ++u) {
             if (q0 + u < cnt) {
                 V a[4], x[4];
-                P::decode4(ra[u], a);
-                P::decode4(rx[u], x);
+                P::decode4_nz(ra[u], a);
+                P::decode4_nz(rx[u], x);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) acc[k] = P::add(acc[k], P::mul_raw(a[k], x[k]));
             }
