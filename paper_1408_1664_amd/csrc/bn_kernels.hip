@@ -1953,6 +1953,60 @@ k_gamma_highA(int n, int d, int a, uint32_t KA, GammaGeom gg, Tables tb,
         dst[(((size_t)s * KA + pi) << hB) + Ht] = vec[tb.pat[pi]];
 }
 
+// Level A for a = 12: the same outputs, from a dense downward zeta over the
+// 12 bits in registers (256 threads x 16 entries; bits 0..3, 4..7, 8..11 in
+// three layouts joined through LDS). A needed output (at most d - sigma
+// ones) receives the same additions in the same order as in the truncated
+// pass above, so the two agree exactly; the other entries are computed too
+// and never read. No pattern table, division or skip test per update.
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_gamma_highA12(int n, uint32_t KA, GammaGeom gg, Tables tb,
+                const typename P::V *__restrict__ Y1, typename P::V *__restrict__ Y2) {
+    using V = typename P::V;
+    constexpr int a = 12, NR = 16;
+    extern __shared__ unsigned char smem[];
+    V *vec = reinterpret_cast<V *>(smem);   // 2^12 entries at padx indices
+    const int v = find_v(gg.blkA, n, blockIdx.x);
+    const uint32_t local = blockIdx.x - gg.blkA[v];
+    const int hv = gg.hv[v];
+    const int hB = hv - a;
+    const uint32_t Ht = local & ((1u << hB) - 1);
+    const uint32_t s = local >> hB;
+    const uint32_t t = threadIdx.x;
+    const V *src = Y1 + gg.y1off[v] + ((size_t)s << hv) + ((size_t)Ht << a);
+    V g[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) g[r] = src[(t << 4) | r];
+    auto zeta4 = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (!((r >> q) & 1)) g[r] = P::add(g[r], g[r | (1 << q)]);
+    };
+    zeta4();                                            // bits 0..3
+#pragma unroll
+    for (int r = 0; r < NR; ++r) vec[padx((t << 4) | r)] = g[r];
+    __syncthreads();
+    const uint32_t tlo = t & 15, thi = t >> 4;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) g[r] = vec[padx((thi << 8) | (r << 4) | tlo)];
+    zeta4();                                            // bits 4..7
+#pragma unroll
+    for (int r = 0; r < NR; ++r) vec[padx((thi << 8) | (r << 4) | tlo)] = g[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) g[r] = vec[padx((r << 8) | t)];
+    zeta4();                                            // bits 8..11
+#pragma unroll
+    for (int r = 0; r < NR; ++r) vec[padx((r << 8) | t)] = g[r];
+    __syncthreads();
+    V *dst = Y2 + gg.y2off[v];
+    for (uint32_t pi = t; pi < KA; pi += kThreads)
+        dst[(((size_t)s * KA + pi) << hB) + Ht] = vec[padx(tb.pat[pi])];
+}
+
 // Level B, workgroup (v, seed): for each a-bit pattern p and each output
 // pattern y over the remaining hB bits, the superset sum over y' of y.
 template <class P>
@@ -2431,8 +2485,14 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
             BN_CHECK_LAUNCH();
         }
         if (gg.blkA[n] > 0) {
-            hipLaunchKernelGGL(k_gamma_highA<P>, dim3(gg.blkA[n]), dim3(kThreads),
-                               sizeof(V) << a.aG, st, n, d, a.aG, a.KA, gg, tb, (const V *)Y1, Y2);
+            if (a.aG == 12)
+                hipLaunchKernelGGL(k_gamma_highA12<P>, dim3(gg.blkA[n]), dim3(kThreads),
+                                   sizeof(V) * (4096 + 256), st, n, a.KA, gg, tb, (const V *)Y1,
+                                   Y2);
+            else
+                hipLaunchKernelGGL(k_gamma_highA<P>, dim3(gg.blkA[n]), dim3(kThreads),
+                                   sizeof(V) << a.aG, st, n, d, a.aG, a.KA, gg, tb,
+                                   (const V *)Y1, Y2);
             BN_CHECK_LAUNCH();
             hipLaunchKernelGGL(k_gamma_highB<P>, dim3(gg.blkB[n]), dim3(kThreads), 0, st, n, d,
                                a.aG, a.KA, a.K, gg, tb, (const V *)Y2, gam);
