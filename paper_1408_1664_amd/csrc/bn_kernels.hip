@@ -734,6 +734,134 @@ __host__ __device__ constexpr uint32_t colex4(uint32_t r) {
     return c;
 }
 
+// Padded LDS index: one spare slot every 16 entries.
+__device__ inline uint32_t padx(uint32_t x) { return x + (x >> 4); }
+
+// Seeds of the linear alpha tiles by blocks of tiles (same outputs as
+// k_alpha_seeds). Workgroup (i, Hh) covers the 2^b tiles H = Hh * 2^b + Hl
+// (b = min(8, hA) >= 4 low bits of H). With G_H = G_lo + G_hi, G_lo over the
+// b low bits of H and G_hi over the rest,
+//   Z(H, G_L) = sum_{G_lo subset Hl} F(G_lo),
+//   F(G_lo) = sum_{G_hi subset Hh, |G_hi| <= d - |G_L| - |G_lo|} betal_i(G_L + G_lo + G_hi),
+// i.e. an upward zeta over the b low bits of a vector that is nonzero only
+// where |G_L| + |G_lo| <= d. The seeds go in chunks of 16: thread (g, u) holds
+// F for seed g and G_lo = u * 16 + r in 16 registers (bits 0..3), then, after
+// an LDS transpose, bits 4..b-1. Score ranks are size, then colex: the part
+// of G_hi (with the size offset) comes from a table built per workgroup,
+// hiP[m][j] for the j-th subset of Hh and m smaller elements.
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_alpha_seeds_blk(int n, int d, uint32_t K, uint32_t KS, int b, uint32_t nhiMax, Tables tb,
+                  const double *__restrict__ betal, const int *__restrict__ linok,
+                  double *__restrict__ Zs) {
+    constexpr int bA = 13;
+    extern __shared__ unsigned char smem[];
+    double *buf = reinterpret_cast<double *>(smem);                   // 16 x 256, padx
+    uint32_t *sbin = reinterpret_cast<uint32_t *>(buf + 4096 + 256);  // 33 x 33
+    uint32_t *hiP = sbin + 33 * 33;                                   // (d + 1) x nhiMax
+    __shared__ uint32_t hcnt[34];
+    __shared__ int hpos[32];
+    __shared__ int snh;
+    const int N = n - 1, hA = N - bA, hh = hA - b;
+    const int i = blockIdx.x >> hh;
+    const uint32_t Hh = blockIdx.x & ((1u << hh) - 1);
+    const int t = threadIdx.x;
+    if (!linok[i]) return;
+    for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
+    if (t == 0) {
+        int c = 0;
+        for (int p = 0; p < hh; ++p)
+            if ((Hh >> p) & 1) hpos[c++] = bA + b + p;   // mask positions of Hh's elements
+        snh = c;
+    }
+    __syncthreads();
+    const uint32_t *bn = sbin;
+    const int nh = snh;
+    const uint32_t nhi = Kcount(bn, nh, d);
+    if (t <= d) hcnt[t] = Kcount(bn, nh, t);         // subsets of Hh with at most t elements
+    for (uint32_t j = t; j < nhi; j += kThreads) {
+        int k = 0;
+        uint32_t off = 0;
+        while (j >= off + C(bn, nh, k)) off += C(bn, nh, k++);
+        int el[8];
+        colex_unrank(bn, j - off, k, el);
+        for (int m = 0; m <= d; ++m) {
+            uint32_t r = (m + k >= 1) ? Kcount(bn, N, m + k - 1) : 0u;
+            for (int q = 0; q < k; ++q) r += C(bn, hpos[el[q]], m + q + 1);
+            hiP[m * nhiMax + j] = r;
+        }
+    }
+    __syncthreads();
+    const double *bi = betal + (size_t)i * K;
+    const uint32_t g = t >> 4, u = t & 15;
+    const uint32_t nu = 1u << (b - 4);                 // thread values of G_lo bits 4..b-1
+    const uint64_t tile0 = (uint64_t)blockIdx.x << b;  // tile index (i, Hh, Hl = 0)
+    const uint32_t nent = 16u << b;
+    for (uint32_t c0 = 0; c0 < KS; c0 += 16) {
+        const uint32_t rk = c0 + g;
+        double v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = 0.0;
+        if (rk < KS && u < nu) {
+            const uint32_t GL = tb.seedA[rk];
+            const int s = __popc(GL);
+            const uint32_t cl = rk - Kcount(bn, bA, s - 1);   // colex rank of G_L
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t Glo = (u << 4) | (uint32_t)r;
+                const int m = s + __popc(Glo);
+                if (m > d) continue;
+                uint32_t lp = cl;
+                int q = s;
+                uint32_t rest = Glo;
+                while (rest) {
+                    const int p = __ffs(rest) - 1;
+                    rest &= rest - 1;
+                    lp += C(bn, bA + p, ++q);
+                }
+                const uint32_t *hp = hiP + m * nhiMax;
+                const uint32_t nsub = hcnt[d - m];
+                double acc = 0.0;
+                for (uint32_t jj = 0; jj < nsub; ++jj) acc += bi[lp + hp[jj]];
+                v[r] = acc;
+            }
+        }
+        // upward zeta over G_lo bits 0..3
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if ((r >> q) & 1) v[r] += v[r ^ (1 << q)];
+        if (u < nu) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[padx((g << 8) | (u << 4) | (uint32_t)r)] = v[r];
+        }
+        __syncthreads();
+        // thread (g, u = G_lo bits 0..3), registers r = G_lo bits 4..b-1
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            v[r] = ((uint32_t)r < nu) ? buf[padx((g << 8) | ((uint32_t)r << 4) | u)] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q < b - 4) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    if ((r >> q) & 1) v[r] += v[r ^ (1 << q)];
+            }
+        }
+        __syncthreads();
+        // tile-major for the stores: entry (Hl, g) at Hl * 16 + g
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if ((uint32_t)r < nu) buf[padx((((uint32_t)r << 4) | u) * 16 + g)] = v[r];
+        __syncthreads();
+        for (uint32_t e = t; e < nent; e += kThreads) {
+            const uint32_t Hl = e >> 4, gg = e & 15;
+            if (c0 + gg < KS) Zs[(tile0 | Hl) * KS + c0 + gg] = buf[padx(e)];
+        }
+        __syncthreads();
+    }
+}
+
 // One 12-bit half of a linear alpha tile (see k_alpha_lin).
 template <class P, int hb>
 __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__ zs,
@@ -1202,7 +1330,6 @@ __device__ inline void reg_zeta_down(typename P::V *g, int q) {
 
 // Padded LDS index: one spare slot every 16 entries keeps the transposed
 // reads of the Gamma tile free of heavy bank conflicts.
-__device__ inline uint32_t padx(uint32_t x) { return x + (x >> 4); }
 
 // Workgroup = full-mask tile H of 2^12 masks (the low 12 bits vary), 256
 // threads x 16 entries. L(H + x) and Rp(H + x) stay in registers for the
@@ -2382,10 +2509,21 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prep_lin<P>), dim3(n), dim3(kThreads), 0, st, n,
                                a.K, (const V *)beta, a.betal, (A *)a.anc, a.linok);
             BN_CHECK_LAUNCH();
-            const size_t smS = 33 * 33 * 4 + (use_prk ? (size_t)(d + 1) * nit * 2 + nit : 0);
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_seeds<P>), dim3(nblkA), dim3(kThreads), smS,
-                               st, n, d, a.K, a.KS, use_prk, tb, (const double *)a.betal,
-                               (const int *)a.linok, a.Zs);
+            const int hA = N - 13, bS = hA < 8 ? hA : 8;
+            const uint32_t nhiMax = host_kcount(hA - bS, d);
+            if (a.KS > 0 && hA >= 4 && d <= 7 && (size_t)(d + 1) * nhiMax <= 4096) {
+                // block-wise seeds: 2^bS tiles per workgroup
+                const size_t smB = 8 * (4096 + 256) + 33 * 33 * 4 + (size_t)(d + 1) * nhiMax * 4;
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_seeds_blk<P>),
+                                   dim3((unsigned)(n << (hA - bS))), dim3(kThreads), smB, st, n,
+                                   d, a.K, a.KS, bS, nhiMax, tb, (const double *)a.betal,
+                                   (const int *)a.linok, a.Zs);
+            } else if (a.KS > 0) {
+                const size_t smS = 33 * 33 * 4 + (use_prk ? (size_t)(d + 1) * nit * 2 + nit : 0);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_seeds<P>), dim3(nblkA), dim3(kThreads),
+                                   smS, st, n, d, a.K, a.KS, use_prk, tb, (const double *)a.betal,
+                                   (const int *)a.linok, a.Zs);
+            }
             BN_CHECK_LAUNCH();
             const size_t smL = 8 * (4096 + 256);
             allow_big_lds<k_alpha_lin<P>>();
