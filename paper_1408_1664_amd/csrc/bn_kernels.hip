@@ -739,7 +739,7 @@ __device__ inline uint32_t padx(uint32_t x) { return x + (x >> 4); }
 
 // Seeds of the linear alpha tiles by blocks of tiles (same outputs as
 // k_alpha_seeds). Workgroup (i, Hh) covers the 2^b tiles H = Hh * 2^b + Hl
-// (b = min(8, hA) >= 4 low bits of H). With G_H = G_lo + G_hi, G_lo over the
+// (4 <= b <= 8 low bits of H). With G_H = G_lo + G_hi, G_lo over the
 // b low bits of H and G_hi over the rest,
 //   Z(H, G_L) = sum_{G_lo subset Hl} F(G_lo),
 //   F(G_lo) = sum_{G_hi subset Hh, |G_hi| <= d - |G_L| - |G_lo|} betal_i(G_L + G_lo + G_hi),
@@ -2509,10 +2509,11 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prep_lin<P>), dim3(n), dim3(kThreads), 0, st, n,
                                a.K, (const V *)beta, a.betal, (A *)a.anc, a.linok);
             BN_CHECK_LAUNCH();
-            const int hA = N - 13, bS = hA < 8 ? hA : 8;
-            const uint32_t nhiMax = host_kcount(hA - bS, d);
-            if (a.KS > 0 && hA >= 4 && d <= 7 && (size_t)(d + 1) * nhiMax <= 4096) {
-                // block-wise seeds: 2^bS tiles per workgroup
+            // block-wise seeds: 2^bS tiles per workgroup, 4 <= bS <= 8, with at
+            // least 4 high bits left so that the grid holds n * 16 workgroups
+            const int hA = N - 13, bS = hA - 4 < 8 ? hA - 4 : 8;
+            const uint32_t nhiMax = bS >= 4 ? host_kcount(hA - bS, d) : 0u;
+            if (a.KS > 0 && bS >= 4 && d <= 7 && (size_t)(d + 1) * nhiMax <= 4096) {
                 const size_t smB = 8 * (4096 + 256) + 33 * 33 * 4 + (size_t)(d + 1) * nhiMax * 4;
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_seeds_blk<P>),
                                    dim3((unsigned)(n << (hA - bS))), dim3(kThreads), smB, st, n,
