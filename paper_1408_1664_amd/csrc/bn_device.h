@@ -113,6 +113,11 @@ struct PolLog {
         const double s = a + b + c;
         return s > -1e300 ? exp(s - T) : 0.0;
     }
+    // prod_lin with the first two factors already multiplied (mul_raw)
+    __device__ static inline double prod2_lin(V ab, V c, Anchor T) {
+        const double s = ab + c;
+        return s > -1e300 ? exp(s - T) : 0.0;
+    }
     __device__ static inline V from_lin(double y, Anchor T) {
         return y > 0.0 ? log(y) + T : zero();
     }
@@ -309,6 +314,12 @@ struct PolX32 {
     }
     __device__ static inline double prod_lin(V a, V b, V c, Anchor T) {
         return ldexp((double)(a.f * b.f * c.f), max(a.e + b.e + c.e - T, -2000));
+    }
+    // prod_lin with the first two factors already multiplied (mul_raw, f up
+    // to 2^64). A zero factor has significand 0, so no exponent clamp is
+    // needed: ldexp of 0 is 0 for any exponent.
+    __device__ static inline double prod2_lin(V ab, V c, Anchor T) {
+        return ldexp((double)(ab.f * c.f), ab.e + c.e - T);
     }
     // Back to a normalised X32 (f in [2^-32, 2^32]); y >= 0 and finite.
     __device__ static inline V from_lin(double y, Anchor T) {

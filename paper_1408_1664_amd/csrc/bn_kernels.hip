@@ -1672,11 +1672,15 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
     }
     __syncthreads();
     // q(|S|) for the thread's entries in layout A: |S| = |H| + |t| + |r|
-    V qa[5];
+    // q(|S|) L(S) for the thread's entries, the factor every endpoint shares
+    V qL[NR];
     {
         const int ht = hpc + __popc(t);
+        V qa[5];
 #pragma unroll
         for (int m = 0; m < 5; ++m) qa[m] = sq[min(ht + m, 31)];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) qL[r] = P::mul_raw(qa[__builtin_popcount(r)], P::at16_nz(Lw, r));
     }
     const uint32_t tlo = t & 15, thi = t >> 4;
     const uint32_t pc = ord8[t];
@@ -1696,16 +1700,14 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
 #pragma unroll
                 for (int r = 0; r < NR; ++r)
                     g[r] = ((r >> q) & 1) ? 0.0
-                                          : P::prod_lin(qa[__builtin_popcount(r)],
-                                                        P::at16_nz(Lw, r),
-                                                        P::at16_nz(Rown, r | (1 << q)), T);
+                                          : P::prod2_lin(qL[r], P::at16_nz(Rown, r | (1 << q)), T);
             }
         } else {
             const bool excl = low && ((t >> (v - 4)) & 1);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 const double pr =
-                    P::prod_lin(qa[__builtin_popcount(r)], P::at16_nz(Lw, r), P::at16_nz(Rv, r), T);
+                    P::prod2_lin(qL[r], P::at16_nz(Rv, r), T);
                 g[r] = excl ? 0.0 : pr;
             }
         }
