@@ -1734,7 +1734,7 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (v != 4 + q) lin_zeta_down<NR>(g, q);
-        __syncthreads();
+        // B-layout slots belong to one thread each: written back in place
 #pragma unroll
         for (int r = 0; r < NR; ++r) gb[padx((thi << 8) | (r << 4) | tlo)] = g[r];
         __syncthreads();
