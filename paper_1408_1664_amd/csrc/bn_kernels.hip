@@ -1136,7 +1136,7 @@ __device__ inline void stage_alpha(const typename P::Store &alpha, uint64_t NN, 
     const uint32_t total = (uint32_t)bL * half;
     const int t = threadIdx.x;
     if (half >= 4) {
-        constexpr int U = 5;                  // 10 * 512 / (4 * 256) for bL = 10
+        constexpr int U = 5;                  // batches of 4 entries in flight per thread
         for (uint32_t e0 = 4 * t; e0 < total; e0 += 4 * kThreads * U) {
             typename P::Raw4 raw[U];
 #pragma unroll
