@@ -199,3 +199,18 @@ def subset_sums_at(x: np.ndarray, kind: str, Ts, d: int = -1, absval: bool = Fal
     if rc:
         raise RuntimeError(f"or_subset_sums_at failed ({rc})")
     return out
+
+
+def modular_feature_posterior(logB: np.ndarray, d: int, log_f: np.ndarray, log_q=None,
+                              nthreads: int = 0) -> dict:
+    """Posterior expectation E[f | D] of a modular feature f(G) = prod_i f_i(G_i)
+    (Sec. 2.1; a 0/1 feature gives its posterior probability). With f put into
+    Eq. 5, P(f, D) is the forward sum F(V) of Eq. 9 run on f_i(G) B_i(G) in
+    place of B_i(G); P(D) is the plain F(V).
+    logB, log_f: [n, 2^n] full-mask arrays (log_f -inf where f_i(G) = 0)."""
+    logB = np.asarray(logB, dtype=np.float64)
+    lf = logB + np.asarray(log_f, dtype=np.float64)
+    base = posteriors_from_scores(logB, d, log_q=log_q, nthreads=nthreads)["log_LV"]
+    feat = posteriors_from_scores(lf, d, log_q=log_q, nthreads=nthreads)["log_LV"]
+    value = math.exp(feat - base) if feat > -math.inf else 0.0
+    return dict(value=value, log_LV=base, log_LfV=feat)

@@ -277,3 +277,76 @@ def test_degenerate_d0_and_full_d():
     ra = O.edge_posteriors(ds.data, ds.arity, 5)
     rb = O.edge_posteriors(ds.data, ds.arity, 9)
     np.testing.assert_array_equal(ra["post"], rb["post"])
+
+
+def _feature_dict(lf, logB_dict):
+    """log f as logf[i][G] on the keys of logB (-inf entries kept)."""
+    n = len(logB_dict)
+    return [{G: float(lf[i, sum(1 << j for j in G)]) for G in logB_dict[i]} for i in range(n)]
+
+
+def _random_feature(n, rng, kind):
+    """log f_i(G) as [n, 2^n]: 'weights' (random f in (0, 2]), 'mask' (random
+    0/1 per (i, G), keeping f_i(empty) = 1), 'edges' (u->v required for a few
+    pairs, i.e. f_v(G) = [u in G])."""
+    lf = np.zeros((n, 1 << n))
+    if kind == "weights":
+        lf = np.log(rng.uniform(0.05, 2.0, size=(n, 1 << n)))
+    elif kind == "mask":
+        lf = np.where(rng.random((n, 1 << n)) < 0.3, -np.inf, 0.0)
+        lf[:, 0] = 0.0
+    else:
+        for _ in range(2):
+            u, v = rng.choice(n, 2, replace=False)
+            has = np.array([(G >> u) & 1 for G in range(1 << n)], dtype=bool)
+            lf[v] = np.where(has, lf[v], -np.inf)
+    return lf
+
+
+@pytest.mark.parametrize("n,d,seed,kind", [(4, 2, 7, "weights"), (5, 3, 8, "mask"),
+                                           (5, 2, 9, "edges"), (6, 2, 10, "weights")])
+def test_modular_feature_orders_brute_force(n, d, seed, kind):
+    """E[f | D] from the forward sum on f_i B_i against Eq. 5 with f summed
+    over all orders (random q)."""
+    rng = np.random.default_rng(seed)
+    logB = B.random_logB(n, d, rng, scale=3.0)
+    lq = rng.normal(size=n)
+    lf = _random_feature(n, rng, kind)
+    r = O.modular_feature_posterior(logB, d, lf, log_q=lq)
+    Bd = B.full_to_dict(logB, n)
+    want = B.orders_feature_posterior(Bd, d, _feature_dict(lf, Bd), log_q=lq)
+    assert r["value"] == pytest.approx(want, rel=1e-11, abs=1e-14)
+
+
+def test_modular_feature_dag_enumeration():
+    ds = datagen.random_dag_dataset(4, 80, 2, 2, 1.0, seed=43)
+    logB = O.full_log_beta(ds.data, ds.arity, 2)
+    rng = np.random.default_rng(44)
+    for kind in ["weights", "mask", "edges"]:
+        lf = _random_feature(4, rng, kind)
+        r = O.modular_feature_posterior(logB, 2, lf)
+        Bd = B.full_to_dict(logB, 4)
+        want = B.dag_feature_posterior(Bd, 2, _feature_dict(lf, Bd))
+        assert r["value"] == pytest.approx(want, rel=1e-11, abs=1e-14)
+
+
+def test_modular_feature_special_cases():
+    """f == 1 gives 1; f_v(G) = [u in G] gives the edge posterior; f_v(G) =
+    [G = G0] gives the parent-set posterior; f_v == 0 gives 0."""
+    n, d = 6, 3
+    rng = np.random.default_rng(45)
+    logB = B.random_logB(n, d, rng, scale=3.0)
+    r0 = O.parent_set_posteriors(logB, d)
+    assert O.modular_feature_posterior(logB, d, np.zeros((n, 1 << n)))["value"] == pytest.approx(1.0, abs=1e-13)
+    for u, v in [(0, 1), (4, 2), (5, 0)]:
+        lf = np.zeros((n, 1 << n))
+        lf[v] = np.where([(G >> u) & 1 for G in range(1 << n)], 0.0, -np.inf)
+        assert O.modular_feature_posterior(logB, d, lf)["value"] == pytest.approx(r0["post"][u, v], abs=1e-12)
+    for v, G0 in [(1, 0b000101), (3, 0)]:
+        lf = np.zeros((n, 1 << n))
+        lf[v] = -np.inf
+        lf[v, G0] = 0.0
+        assert O.modular_feature_posterior(logB, d, lf)["value"] == pytest.approx(r0["ps"][v, G0], abs=1e-12)
+    lf = np.zeros((n, 1 << n))
+    lf[2] = -np.inf
+    assert O.modular_feature_posterior(logB, d, lf)["value"] == 0.0
