@@ -218,6 +218,30 @@ bn_status bn_serve_poll(void *server, uint64_t ticket, double *post, bn_report *
 bn_status bn_server_destroy(void *server);
 
 /*
+ * Posterior expectation of a modular feature f(G) = prod_i f_i(G_i), a
+ * product of one factor per node that depends only on that node's parent
+ * set (Sec. 2.1; for a 0/1 feature it is the posterior probability P(f | D),
+ * Eqs. 1-2). With the order-modular prior (Eq. 4) f enters Eq. 5 next to
+ * B_i, so P(f, D) is the forward sum L(V) of Eq. 9 run on f_i(G) B_i(G);
+ * the result is P(f, D) / P(D). Two forward-only runs (alpha and the
+ * forward sweep; no backward sweep or Gamma). Examples: f_v(G) = [u in G]
+ * gives P(u -> v | D); f_v(G) = [u not in G] for several pairs gives the
+ * probability that none of those edges is present.
+ *   log_f: host, n * K(n-1,d) doubles, log f_i(G) for the parent set of rank
+ *          r (the ranking of bn_local_scores) at log_f[i*K + r]; -inf where
+ *          f_i(G) = 0, 0 where it is 1. Read only.
+ *   expectation: host, one double, E[f | D] (0 when P(f, D) = 0).
+ *   log_pair: nullable host double[2], {log P(D), log P(f, D)} up to the
+ *          same constant.
+ * Allocates and frees its own workspace; blocks until done. BN_EINVAL as for
+ * bn_edge_posteriors, and for a NULL log_f or expectation or an entry of
+ * log_f that is NaN or +inf (checked before any device work).
+ */
+bn_status bn_modular_feature_posterior(const bn_problem *p, bn_precision prec,
+                                       const double *log_f, double *expectation,
+                                       double *log_pair);
+
+/*
  * Subset transforms of a device array x of 2^nbits doubles, x[S] for the
  * subset S given by the bits of the index, in place on the given stream
  * (NULL: the default stream); returns without waiting.

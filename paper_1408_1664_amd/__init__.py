@@ -30,7 +30,8 @@ EXPORTED = ["bn_num_parent_sets", "bn_local_scores", "bn_workspace_bytes",
             "bn_edge_posteriors", "bn_parent_set_posteriors", "bn_edge_posteriors_dev",
             "bn_timer_create",
             "bn_timer_destroy", "bn_timer_read", "bn_server_create", "bn_serve_submit",
-            "bn_serve_poll", "bn_server_destroy", "bn_subset_transform", "bn_status_string"]
+            "bn_serve_poll", "bn_server_destroy", "bn_subset_transform",
+            "bn_modular_feature_posterior", "bn_status_string"]
 
 
 class BnError(RuntimeError):
@@ -105,6 +106,8 @@ def lib():
         L.bn_serve_poll.restype = ctypes.c_int
         L.bn_server_destroy.argtypes = [P]
         L.bn_server_destroy.restype = ctypes.c_int
+        L.bn_modular_feature_posterior.argtypes = [P, ctypes.c_int, P, P, P]
+        L.bn_modular_feature_posterior.restype = ctypes.c_int
         L.bn_subset_transform.argtypes = [P, I32, ctypes.c_int, I32, P]
         L.bn_subset_transform.restype = ctypes.c_int
         L.bn_status_string.argtypes = [ctypes.c_int]
@@ -251,6 +254,27 @@ def edge_posteriors_dev(data_dev, arity, d, precision, ws, post_dev, diag_dev=No
                                         else ctypes.c_void_p(diag_dev.data_ptr()),
                                         None if timer is None else timer._h),
            "bn_edge_posteriors_dev")
+
+
+def modular_feature_posterior(data, arity, d, log_f, precision="fp64", score="bdeu", ess=1.0,
+                              log_rho=None, log_q=None) -> dict:
+    """E[f | D] for f(G) = prod_i f_i(G_i) (bn_modular_feature_posterior).
+
+    log_f: [n, K] array, log f_i(G) in the rank order of local_scores (-inf
+    for a zero factor). Returns dict(value, log_PD, log_PfD)."""
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    n = data.shape[0]
+    K = num_parent_sets(n, d)
+    lf = np.ascontiguousarray(log_f, dtype=np.float64)
+    if lf.shape != (n, K):
+        raise ValueError(f"log_f must have shape ({n}, {K})")
+    h = _ProblemHold(data, arity, d, score, ess, log_rho, log_q)
+    out = np.zeros(1)
+    pair = np.zeros(2)
+    _check(lib().bn_modular_feature_posterior(h.ref(), _PREC[precision], _ptr(lf), _ptr(out),
+                                              _ptr(pair)),
+           "bn_modular_feature_posterior")
+    return dict(value=float(out[0]), log_PD=float(pair[0]), log_PfD=float(pair[1]))
 
 
 SUBSET_KINDS = {"zeta_up": 0, "zeta_down": 1, "mobius_up": 2, "mobius_down": 3}

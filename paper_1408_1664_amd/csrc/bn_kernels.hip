@@ -2288,6 +2288,37 @@ __global__ void k_finalize(int n, typename P::Store L, typename P::Store R,
     diag[7] = (double)((fbA ? fbA[0] : 0u) + (fbG ? fbG[0] : 0u));
 }
 
+// Forward-only runs (modular features): diag[0] = log L(V) with the gauges,
+// [2] / [3] the saturation and flush counts, [7] the fallback tiles; the
+// invariant entries are 0 (no backward sweep to check against).
+template <class P>
+__global__ void k_log_LV(int n, typename P::Store L, const double *__restrict__ gauge_exp,
+                         const unsigned long long *__restrict__ cnt,
+                         const uint32_t *__restrict__ fbA, double *__restrict__ diag) {
+    if (threadIdx.x != 0) return;
+    double g = 0.0;
+    for (int k = 0; k < 2 * n; ++k) g += gauge_exp[k];
+    diag[0] = P::to_log(P::load(L, (1ull << n) - 1)) + g * 0.69314718055994530942;
+    diag[1] = diag[4] = diag[5] = diag[6] = 0.0;
+    diag[2] = (double)cnt[0];
+    diag[3] = (double)cnt[1];
+    diag[7] = (double)(fbA ? fbA[0] : 0u);
+}
+
+__global__ void k_add_log(double *__restrict__ logp, const double *__restrict__ log_f,
+                          size_t count) {
+    for (size_t x = (size_t)blockIdx.x * kThreads + threadIdx.x; x < count;
+         x += (size_t)gridDim.x * kThreads)
+        logp[x] += log_f[x];
+}
+
+hipError_t launch_add_log(double *logp, const double *log_f, size_t count, hipStream_t st) {
+    const unsigned g = (unsigned)std::min<size_t>((count + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(k_add_log, dim3(std::max(g, 1u)), dim3(kThreads), 0, st, logp, log_f,
+                       count);
+    return hipGetLastError();
+}
+
 // ------------------------------------------- a1: local scores, binary data
 // All-binary data as two bit planes per variable: plane 1 marks the samples
 // with value 1, plane 0 those with value 0 (a value out of range is in
@@ -2572,6 +2603,14 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
         BN_CHECK_LAUNCH();
     }
     rec(3);
+    if (a.fwd_only) {
+        hipLaunchKernelGGL(k_log_LV<P>, dim3(1), dim3(64), 0, st, n, L,
+                           (const double *)a.gauge_exp, (const unsigned long long *)a.cnt,
+                           (const uint32_t *)a.fbA, a.diag);
+        BN_CHECK_LAUNCH();
+        rec(6);
+        return hipSuccess;
+    }
     for (int h = nh; h >= 0; --h) {
         const unsigned nb = a.tiles_per_layer[h];
         hipLaunchKernelGGL(k_bwd<P>, dim3(nb), dim3(kThreads), smL, st, n, a.bL, h, tb, alpha, R,

@@ -296,12 +296,8 @@ static bn_status enqueue_scores(const Plan &P, const bn_problem *p, const uint8_
     return BN_OK;
 }
 
-bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_data, char *ws,
-                        hipStream_t st, double *dev_post, double *dev_diag, PhaseEvents *ev,
-                        double *dev_ps) {
-    if (ev && ev->ev[0]) HIPCHK(hipEventRecord(ev->ev[0], st));
-    bn_status s = enqueue_scores(P, p, dev_data, ws, st);
-    if (s != BN_OK) return s;
+static LatticeArgs lattice_args(const Plan &P, char *ws, double *dev_post, double *dev_diag,
+                                double *dev_ps) {
     LatticeArgs a{};
     a.n = P.n;
     a.d = P.d;
@@ -342,6 +338,11 @@ bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_d
     a.linok = reinterpret_cast<int *>(ws + P.o_linok);
     a.Zs = P.alpha_lin ? reinterpret_cast<double *>(ws + P.o_Zs) : nullptr;
     a.KS = P.KS;
+    return a;
+}
+
+static bn_status run_lattice(const Plan &P, char *ws, const LatticeArgs &a, hipStream_t st,
+                             PhaseEvents *ev) {
     hipError_t e;
     if (P.x32) {
         PolX32::Store al{reinterpret_cast<float *>(ws + P.o_alpha_f),
@@ -358,6 +359,16 @@ bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_d
         e = launch_lattice<PolLog>(a, al, L, R, st, ev);
     }
     return e == hipSuccess ? BN_OK : BN_EDEVICE;
+}
+
+bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_data, char *ws,
+                        hipStream_t st, double *dev_post, double *dev_diag, PhaseEvents *ev,
+                        double *dev_ps) {
+    if (ev && ev->ev[0]) HIPCHK(hipEventRecord(ev->ev[0], st));
+    bn_status s = enqueue_scores(P, p, dev_data, ws, st);
+    if (s != BN_OK) return s;
+    const LatticeArgs a = lattice_args(P, ws, dev_post, dev_diag, dev_ps);
+    return run_lattice(P, ws, a, st, ev);
 }
 
 bn_status local_scores_host(const bn_problem *p, double *log_score) {
@@ -454,6 +465,60 @@ bn_status edge_posteriors_host(const bn_problem *p, bn_precision prec, double *p
     return rs;
 }
 
+// E[f | D] of a modular feature: two forward-only runs on one workspace, the
+// second with log f added to the log scores (f_i(G) B_i(G) in place of
+// B_i(G)); out = exp(log P(f, D) - log P(D)).
+bn_status feature_posterior_host(const bn_problem *p, bn_precision prec, const double *log_f,
+                                 double *out, double *log_pair) {
+    bn_status s = validate(p, true, true);
+    if (s != BN_OK) return s;
+    if (!log_f || !out) return BN_EINVAL;
+    if (prec != BN_FP64_LOG && prec != BN_FP32_SCALED) return BN_EINVAL;
+    Plan P = make_plan(p->n, p->d, p->m, prec, true, true);
+    const size_t cnt = (size_t)P.n * P.K;
+    for (size_t x = 0; x < cnt; ++x)
+        if (std::isnan(log_f[x]) || log_f[x] == HUGE_VAL) return BN_EINVAL;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return BN_EDEVICE;
+    if (P.total > free_b) return BN_ENOMEM;
+    char *ws = nullptr;
+    if (hipMalloc(&ws, P.total) != hipSuccess) return BN_ENOMEM;
+    hipStream_t st = nullptr;
+    uint8_t *dev_data = reinterpret_cast<uint8_t *>(ws + P.o_data);
+    double *dev_diag = reinterpret_cast<double *>(ws + P.o_diag);
+    double *dev_f = reinterpret_cast<double *>(ws + P.o_ps);   // n*K doubles, unused here
+    LatticeArgs a = lattice_args(P, ws, nullptr, dev_diag, nullptr);
+    a.fwd_only = 1;
+    double d0[8] = {0}, d1[8] = {0};
+    bn_status rs = BN_OK;
+    if (P.m > 0 &&
+        hipMemcpyAsync(dev_data, p->data, (size_t)P.n * P.m, hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+        rs = BN_EDEVICE;
+    if (rs == BN_OK) rs = enqueue_scores(P, p, dev_data, ws, st);
+    if (rs == BN_OK) rs = run_lattice(P, ws, a, st, nullptr);
+    if (rs == BN_OK && hipMemcpyAsync(d0, dev_diag, 64, hipMemcpyDeviceToHost, st) != hipSuccess)
+        rs = BN_EDEVICE;
+    if (rs == BN_OK &&
+        hipMemcpyAsync(dev_f, log_f, cnt * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+        rs = BN_EDEVICE;
+    if (rs == BN_OK &&
+        launch_add_log(reinterpret_cast<double *>(ws + P.o_logp), dev_f, cnt, st) != hipSuccess)
+        rs = BN_EDEVICE;
+    if (rs == BN_OK) rs = run_lattice(P, ws, a, st, nullptr);
+    if (rs == BN_OK && hipMemcpyAsync(d1, dev_diag, 64, hipMemcpyDeviceToHost, st) != hipSuccess)
+        rs = BN_EDEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) rs = BN_EDEVICE;
+    (void)hipFree(ws);
+    if (rs != BN_OK) return rs;
+    *out = d1[0] > -HUGE_VAL ? std::exp(d1[0] - d0[0]) : 0.0;
+    if (log_pair) {
+        log_pair[0] = d0[0];
+        log_pair[1] = d1[0];
+    }
+    return BN_OK;
+}
+
 bn_status edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *dev_ws,
                               size_t ws_bytes, void *hip_stream, double *dev_post,
                               double *dev_diag, PhaseEvents *ev) {
@@ -498,6 +563,12 @@ bn_status bn_parent_set_posteriors(const bn_problem *p, bn_precision prec, doubl
                                    double *post, bn_report *rep) {
     if (!ps) return BN_EINVAL;
     return bnk::edge_posteriors_host(p, prec, post, rep, ps);
+}
+
+bn_status bn_modular_feature_posterior(const bn_problem *p, bn_precision prec,
+                                       const double *log_f, double *expectation,
+                                       double *log_pair) {
+    return bnk::feature_posterior_host(p, prec, log_f, expectation, log_pair);
 }
 
 struct bn_timer {

@@ -129,3 +129,22 @@ def test_subset_transform_rejects_bad_arguments():
     assert L.bn_subset_transform(fake, 10, 4, -1, None) == bn.BN_EINVAL
     assert L.bn_subset_transform(fake, 10, 2, 3, None) == bn.BN_EINVAL   # truncated inverse
     assert L.bn_subset_transform(fake, 10, 3, 0, None) == bn.BN_EINVAL
+
+
+def test_modular_feature_rejects_bad_arguments():
+    import ctypes
+    data = np.zeros((4, 10), np.uint8)
+    arity = np.full(4, 2, np.uint8)
+    h = bn._ProblemHold(data, arity, 2, "bdeu", 1.0, None, None)
+    K = bn.num_parent_sets(4, 2)
+    out = np.zeros(1)
+    lf = np.zeros((4, K))
+    L = bn.lib()
+    assert L.bn_modular_feature_posterior(h.ref(), 1, None, bn._ptr(out), None) == bn.BN_EINVAL
+    assert L.bn_modular_feature_posterior(h.ref(), 1, bn._ptr(lf), None, None) == bn.BN_EINVAL
+    for bad in [np.nan, np.inf]:
+        lf2 = lf.copy()
+        lf2[2, 3] = bad
+        assert L.bn_modular_feature_posterior(h.ref(), 1, bn._ptr(lf2), bn._ptr(out), None) == bn.BN_EINVAL
+    with pytest.raises(ValueError):
+        bn.modular_feature_posterior(data, arity, 2, np.zeros((4, K + 1)))

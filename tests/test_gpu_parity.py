@@ -235,3 +235,81 @@ def test_device_entry_matches_host_entry():
         torch.cuda.synchronize()
         assert np.array_equal(post.cpu().numpy(), host)
         assert diag[0].item() == pytest.approx(rep["log_LV"], abs=1e-12)
+
+
+_FEATURE_REF = {}
+
+
+def _ranked_feature(n, d, rng, kind):
+    """log f as [n, K] in rank order and as the [n, 2^n] full-mask array of
+    the oracle. kind: 'weights' (f in (0, 2]), 'mask' (random zeros, f(empty)
+    = 1), 'noedges' (f_v(G) = [u not in G] for a few pairs)."""
+    masks = ranked_masks(n - 1, d)
+    K = len(masks)
+    full = np.zeros((n, 1 << n))
+    if kind == "weights":
+        lf = np.log(rng.uniform(0.05, 2.0, size=(n, K)))
+    elif kind == "mask":
+        lf = np.where(rng.random((n, K)) < 0.3, -np.inf, 0.0)
+        lf[:, 0] = 0.0
+    else:
+        lf = np.zeros((n, K))
+        for _ in range(3):
+            u, v = rng.choice(n, 2, replace=False)
+            pu = u if u < v else u - 1          # u's bit in v's compressed masks
+            lf[v] = np.where((masks >> pu) & 1, -np.inf, lf[v])
+    for v in range(n):
+        full[v, expand(masks, v)] = lf[v]
+    return lf, full
+
+
+@pytest.mark.parametrize("name", ["n12_binary_m200_d3", "n20_ternary_m1000_d4"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", ["weights", "mask", "noedges"])
+def test_modular_feature_matches_oracle(name, prec, kind):
+    """E[f | D] of modular features against the oracle (forward sums with and
+    without f); relative tolerance of the number system on the ratio."""
+    ds, p = datagen.workload(name)
+    n, d = ds.n, p["d"]
+    rng = np.random.default_rng(sum(map(ord, name + kind)))
+    lf, full = _ranked_feature(n, d, rng, kind)
+    key = (name, kind)
+    if key not in _FEATURE_REF:     # the oracle once per workload and feature
+        logB = O.full_log_beta(ds.data, ds.arity, d, ess=p["ess"])
+        _FEATURE_REF[key] = O.modular_feature_posterior(logB, d, full)
+    ref = _FEATURE_REF[key]
+    got = bn.modular_feature_posterior(ds.data, ds.arity, d, lf, precision=prec, ess=p["ess"])
+    print(f"  {name} {prec} {kind}: {got['value']:.12g} vs {ref['value']:.12g}", flush=True)
+    assert got["value"] == pytest.approx(ref["value"], rel=TOL[prec], abs=1e-300)
+    assert got["log_PD"] - got["log_PfD"] == pytest.approx(ref["log_LV"] - ref["log_LfV"],
+                                                           abs=TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_modular_feature_edges_and_sets_agree_with_solve(prec):
+    """f_v(G) = [u in G] gives the edge posterior of the full solve, f_v(G) =
+    [G = G0] its parent-set posterior, f = 1 gives 1 (n = 25, GPU against
+    GPU, both through the C ABI)."""
+    ds, p = datagen.workload("n25_binary_m2000_d4")
+    n, d = ds.n, p["d"]
+    ps, post, _ = bn.parent_set_posteriors(ds.data, ds.arity, d, precision=prec, ess=p["ess"])
+    masks = ranked_masks(n - 1, d)
+    K = len(masks)
+    one = bn.modular_feature_posterior(ds.data, ds.arity, d, np.zeros((n, K)), precision=prec,
+                                       ess=p["ess"])
+    assert one["value"] == pytest.approx(1.0, abs=TOL[prec])
+    order = np.argsort(-post, axis=None)[:3]
+    for flat in order:
+        u, v = divmod(int(flat), n)
+        pu = u if u < v else u - 1
+        lf = np.zeros((n, K))
+        lf[v] = np.where((masks >> pu) & 1, 0.0, -np.inf)
+        r = bn.modular_feature_posterior(ds.data, ds.arity, d, lf, precision=prec, ess=p["ess"])
+        print(f"  edge {u}->{v}: {r['value']:.9f} vs {post[u, v]:.9f}", flush=True)
+        assert r["value"] == pytest.approx(post[u, v], abs=TOL[prec] * 10)
+    v, r0 = divmod(int(np.argmax(ps)), K)
+    lf = np.zeros((n, K))
+    lf[v] = -np.inf
+    lf[v, r0] = 0.0
+    r = bn.modular_feature_posterior(ds.data, ds.arity, d, lf, precision=prec, ess=p["ess"])
+    assert r["value"] == pytest.approx(ps[v, r0], abs=TOL[prec] * 10)
