@@ -109,6 +109,10 @@ struct PolLog {
     __device__ static inline double to_lin(V x, Anchor T) {
         return x > -1e300 ? exp(x - T) : 0.0;
     }
+    // a scale that puts the value 2^e2 at 2^940 (room for 4096 such terms)
+    __device__ static inline Anchor anchor_high(int e2) {
+        return (double)(e2 - 940) * 0.69314718055994530942;
+    }
     __device__ static inline double prod_lin(V a, V b, V c, Anchor T) {
         const double s = a + b + c;
         return s > -1e300 ? exp(s - T) : 0.0;
@@ -312,6 +316,9 @@ struct PolX32 {
     __device__ static inline double to_lin(V x, Anchor T) {
         return ldexp((double)x.f, max(x.e - T, -2000));
     }
+    // a scale (a multiple of 64) that puts the value 2^e2 within 2^888 ..
+    // 2^951 (room for 4096 such terms below 2^1000)
+    __device__ static inline Anchor anchor_high(int e2) { return ((e2 - 888) >> 6) << 6; }
     __device__ static inline double prod_lin(V a, V b, V c, Anchor T) {
         return ldexp((double)(a.f * b.f * c.f), max(a.e + b.e + c.e - T, -2000));
     }

@@ -202,13 +202,15 @@ __global__ void k_prep(int n, int d, uint32_t K, const uint32_t *binom,
                        const double *__restrict__ logp, const double *__restrict__ log_rho,
                        const double *__restrict__ log_q, int gauge,
                        typename P::V *__restrict__ beta, typename P::V *__restrict__ qt,
-                       double *__restrict__ gauge_exp, uint32_t *fbA, uint32_t *fbG) {
+                       double *__restrict__ gauge_exp, uint32_t *fbA, uint32_t *fbG,
+                       uint32_t *rtG) {
     __shared__ double red[kThreads];
     const int i = blockIdx.x;
     const int t = threadIdx.x;
     if (i == 0 && t == 0) {
         if (fbA) fbA[0] = 0;
         if (fbG) fbG[0] = 0;
+        if (rtG) rtG[0] = 0;
     }
     const int N = n - 1;
     double mx = -__builtin_huge_val();
@@ -1351,7 +1353,8 @@ __device__ __forceinline__ void gamma_tile(int n, int d, const GammaGeom &gg, co
                                            const typename P::Store &R,
                                            const typename P::V *__restrict__ qt,
                                            typename P::V *__restrict__ Y1,
-                                           typename P::V *__restrict__ part, uint32_t H) {
+                                           typename P::V *__restrict__ part, uint32_t H,
+                                           int only_v = -1) {
     using V = typename P::V;
     using Raw = typename P::Raw;
     constexpr int bT = 12, NR = 16;
@@ -1383,7 +1386,8 @@ __device__ __forceinline__ void gamma_tile(int n, int d, const GammaGeom &gg, co
             Rr[r] = P::decode_raw(r0[r]);
         }
     }
-    int vn = bT;                              // next endpoint above the tile, not in H
+    // next endpoint above the tile, not in H (only_v itself when it is one)
+    int vn = only_v >= bT ? only_v : bT;
     while (vn < n && ((Hf >> vn) & 1)) ++vn;
     if (vn < n) {
 #pragma unroll
@@ -1422,7 +1426,7 @@ __device__ __forceinline__ void gamma_tile(int n, int d, const GammaGeom &gg, co
         offT1[t] = Kcount(sbin, bT - 1, t - 1);
     }
     const uint32_t tlo = t & 15, thi = t >> 4;
-    for (int v = 0; v < n; ++v) {
+    for (int v = only_v >= 0 ? only_v : 0; v < (only_v >= 0 ? only_v + 1 : n); ++v) {
         const bool low = v < bT;
         if (!low && ((Hf >> v) & 1)) continue;
         // ---- g in layout A
@@ -1528,8 +1532,9 @@ k_gamma_tile(int n, int d, GammaGeom gg, Tables tb, typename P::Store L, typenam
     gamma_tile<P>(n, d, gg, tb, L, R, qt, Y1, part, H);
 }
 
-// Recomputation of the tiles listed by k_gamma_tile_lin (list[0] entries,
-// list[1 + j] = H): the grid walks the list.
+// Recomputation in the number system proper of the listed work (list[0]
+// entries, list[1 + j] = H * 64 + e: tile H, every endpoint for e = 0, else
+// endpoint e - 1 alone): the grid walks the list.
 template <class P>
 __global__ void __launch_bounds__(kThreads)
 k_gamma_tile_fb(int n, int d, GammaGeom gg, Tables tb, typename P::Store L,
@@ -1539,7 +1544,8 @@ k_gamma_tile_fb(int n, int d, GammaGeom gg, Tables tb, typename P::Store L,
     const uint32_t ntile = list[0];
     for (uint32_t it = blockIdx.x; it < ntile; it += gridDim.x) {
         __syncthreads();
-        gamma_tile<P>(n, d, gg, tb, L, R, qt, Y1, part, list[1 + it]);
+        const uint32_t item = list[1 + it];
+        gamma_tile<P>(n, d, gg, tb, L, R, qt, Y1, part, item >> 6, (int)(item & 63) - 1);
     }
 }
 
@@ -1559,8 +1565,9 @@ __device__ inline void lin_zeta_down(double *g, int q) {
 // lose bits to the subnormal range; that changes no output by more than
 // 2^-60 of itself. If Gamma_v(H + empty), the largest entry, overflows after
 // the scaling, or g_v(H + top) is zero, the endpoint's outputs are not stored
-// and the tile goes to the fallback list: k_gamma_tile_fb recomputes all of
-// its endpoints. force_fb sends every tile there (tests).
+// and (H, v) goes to the list of k_gamma_tile_retry. force_fb sends every
+// tile to the fallback list of k_gamma_tile_fb, which recomputes all of its
+// endpoints (tests).
 // Layouts (x the 12 tile bits, 256 threads x 16 entries):
 //   A  x = t * 16 + r      bits 0..3 in registers; products formed here. Each
 //      thread owns 16 consecutive masks, so L, Rp and the partners Rp(x + v)
@@ -1578,7 +1585,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
 k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P::Store L,
                  typename P::Store R, const typename P::V *__restrict__ qt,
                  typename P::V *__restrict__ Y1, typename P::V *__restrict__ part,
-                 uint32_t *fb) {
+                 uint32_t *fb, uint32_t *rt) {
     using V = typename P::V;
     using R16 = typename P::Raw16;
     using A = typename P::Anchor;
@@ -1753,7 +1760,7 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
         // Gamma_v(H + empty) bounds every entry of the tile.
         const bool fine = okv && gb[padx(0)] <= 1.0e300;
         if (!fine) {
-            if (t == 0) sfail = 1;
+            if (t == 0) fb_push(rt, (H << 5) | (uint32_t)v);   // k_gamma_tile_retry
         } else {
             const int hv = gg.hv[v];
             const uint32_t Hc = low ? H : (uint32_t)compress_bit(H, v - bT);
@@ -1778,7 +1785,141 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
         }
         __syncthreads();
     }
-    if (t == 0 && sfail) fb_push(fb, H);
+    if (t == 0 && sfail) fb_push(fb, H << 6);             // every endpoint
+}
+
+// Second chance for the endpoints that k_gamma_tile_lin could not scale from
+// g_v(H + top) (list[0] items, list[1 + j] = H * 32 + v; the grid walks the
+// list). The scale now comes from the largest product of the tile, which
+// keeps Gamma_v(H + empty) finite; the outputs are stored only if every
+// needed one is at least 2^-1000, since the products that fell below 2^-1074
+// (at most 4096) then change none by more than 2^-62 of itself. Otherwise
+// (H, v) goes to the fallback list of k_gamma_tile_fb. Same layouts as
+// k_gamma_tile_lin, layout C for every thread.
+template <class P>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_gamma_tile_retry(int n, int d, GammaGeom gg, Tables tb, typename P::Store L,
+                   typename P::Store R, const typename P::V *__restrict__ qt,
+                   typename P::V *__restrict__ Y1, const uint32_t *list, uint32_t *fb) {
+    using V = typename P::V;
+    using R16 = typename P::Raw16;
+    using A = typename P::Anchor;
+    constexpr int bT = 12, NR = 16;
+    extern __shared__ unsigned char smem[];
+    double *gb = reinterpret_cast<double *>(smem);             // padded 2^12 entries
+    uint32_t *sbin = reinterpret_cast<uint32_t *>(gb + 4096 + 256);
+    uint32_t *seedT = sbin + 33 * 33;                          // K(12, d) ranked masks
+    __shared__ V sq[32];
+    __shared__ uint32_t offT1[34];
+    __shared__ int smax;
+    const uint32_t t = threadIdx.x;
+    for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
+    for (uint32_t x = t; x < gg.KT; x += kThreads) seedT[x] = tb.seedmask[x];
+    if (t < (uint32_t)n) sq[t] = qt[t];
+    __syncthreads();
+    if (t <= (uint32_t)d + 1) offT1[t] = Kcount(sbin, bT - 1, (int)t - 1);
+    const uint32_t tlo = t & 15, thi = t >> 4;
+    const uint32_t nitem = list[0];
+    for (uint32_t it = blockIdx.x; it < nitem; it += gridDim.x) {
+        __syncthreads();
+        const uint32_t item = list[1 + it];
+        const uint32_t H = item >> 5;
+        const int v = (int)(item & 31);
+        const bool low = v < bT;
+        const uint64_t Hf = (uint64_t)H << bT;
+        const uint64_t x0 = Hf | (t << 4);
+        const int ht = __popcll(Hf) + __popc(t);
+        const R16 Lw = P::load16_raw(L, x0);
+        const R16 Rown = P::load16_raw(R, x0);
+        R16 Rv = Rown;
+        if (v >= 4)
+            Rv = P::load16_raw(R, low ? Hf | ((uint64_t)(t | (1u << (v - 4))) << 4) : x0 | (1ull << v));
+        const bool excl = v >= 4 && low && ((t >> (v - 4)) & 1);
+        // products q(|S|) L(S) Rp(S + v) as undecoded values, and their largest
+        V pv[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            pv[r] = P::mul_raw(sq[min(ht + __builtin_popcount(r), 31)], P::at16_nz(Lw, r));
+        if (v < 4) {
+            // the partner of register r is register r + 2^v of the own block
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (v != q) continue;
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    pv[r] = ((r >> q) & 1) ? P::zero()
+                                           : P::mul_raw(pv[r], P::at16_nz(Rown, r | (1 << q)));
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                pv[r] = excl ? P::zero() : P::mul_raw(pv[r], P::at16_nz(Rv, r));
+        }
+        double mx = -1e300;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) mx = fmax(mx, P::log2_of(pv[r]));
+        if (t == 0) smax = -(1 << 30);
+        __syncthreads();
+        atomicMax(&smax, (int)fmax(mx, -1073741824.0));
+        __syncthreads();
+        const bool any = smax > -(1 << 29);
+        const A T = P::anchor_high(smax);
+        double g[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) g[r] = P::prod2_lin(pv[r], P::one(), T);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (v != q) lin_zeta_down<NR>(g, q);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gb[padx((t << 4) | r)] = g[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NR; ++r) g[r] = gb[padx((thi << 8) | (r << 4) | tlo)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (v != 4 + q) lin_zeta_down<NR>(g, q);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gb[padx((thi << 8) | (r << 4) | tlo)] = g[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NR; ++r) g[r] = gb[padx((r << 8) | t)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (v != 8 + q) lin_zeta_down<NR>(g, q);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gb[padx((r << 8) | t)] = g[r];
+        __syncthreads();
+        bool small = !(any && gb[padx(0)] <= 1.0e300);
+        for (uint32_t si = t; si < gg.KT && !small; si += kThreads) {
+            const uint32_t msk = seedT[si];
+            if (low && ((msk >> v) & 1)) continue;
+            small = !(gb[padx(msk)] >= 0x1p-1000);
+        }
+        if (__syncthreads_or(small ? 1 : 0)) {
+            if (t == 0) fb_push(fb, (H << 6) | (uint32_t)(v + 1));   // this endpoint only
+            continue;
+        }
+        const int hv = gg.hv[v];
+        const uint32_t Hc = low ? H : (uint32_t)compress_bit(H, v - bT);
+        V *dst = Y1 + gg.y1off[v];
+        for (uint32_t si = t; si < gg.KT; si += kThreads) {
+            const uint32_t msk = seedT[si];
+            uint32_t rank = si;
+            if (low) {
+                if ((msk >> v) & 1) continue;
+                const uint32_t cm = (uint32_t)compress_bit(msk, v);
+                rank = offT1[__popc(cm)];
+                int k = 0;
+                uint32_t rest = cm;
+                while (rest) {
+                    const int p = __ffs(rest) - 1;
+                    rest &= rest - 1;
+                    rank += C(sbin, p, ++k);
+                }
+            }
+            dst[((size_t)rank << hv) + Hc] = P::from_lin(gb[padx(msk)], T);
+        }
+    }
 }
 
 // ------------------------- a5 + a6: Gamma, in-tile part, tiles of any size
@@ -2527,7 +2668,7 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     hipLaunchKernelGGL(k_prep<P>, dim3(n), dim3(kThreads), 0, st, n, d, a.K,
                        (const uint32_t *)tb.binom, (const double *)a.logp,
                        (const double *)a.log_rho, (const double *)a.log_q, a.gauge, beta, qt,
-                       a.gauge_exp, a.fbA, a.fbG);
+                       a.gauge_exp, a.fbA, a.fbG, a.rtG);
     BN_CHECK_LAUNCH();
     rec(1);
     if (a.bA == 13) {
@@ -2628,9 +2769,14 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
                 allow_big_lds<k_gamma_tile_lin<P>>();
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile_lin<P>), dim3(nblkG),
                                    dim3(kThreads), sm, st, n, d, a.lin_mode == 2 ? 1 : 0, gg, tb,
-                                   L, R, (const V *)qt, Y1, part, a.fbG);
+                                   L, R, (const V *)qt, Y1, part, a.fbG, a.rtG);
                 BN_CHECK_LAUNCH();
                 rec(7);
+                allow_big_lds<k_gamma_tile_retry<P>>();
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile_retry<P>),
+                                   dim3(std::min(nblkG, 1024u)), dim3(kThreads), sm, st, n, d, gg,
+                                   tb, L, R, (const V *)qt, Y1, (const uint32_t *)a.rtG, a.fbG);
+                BN_CHECK_LAUNCH();
                 allow_big_lds<k_gamma_tile_fb<P>>();
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile_fb<P>),
                                    dim3(std::min(nblkG, 1024u)), dim3(kThreads), sm, st, n, d, gg,

@@ -222,7 +222,11 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.o_Zs = P.alpha_lin ? take(zs_bytes) : 0;
     P.o_anc = take(32 * 8);
     P.o_linok = take(32 * 4);
-    P.o_fbG = P.bG == 12 ? take(4 * (1 + ((size_t)1 << (n - 12)))) : 0;
+    // Gamma lists: endpoints for a second scale (at most one entry per tile and
+    // endpoint), tiles for the fallback (one per failed second chance, and one
+    // per tile when every tile is forced there)
+    P.o_fbG = P.bG == 12 ? take(4 * (1 + ((size_t)(n + 1) << (n - 12)))) : 0;
+    P.o_rtG = P.bG == 12 ? take(4 * (1 + ((size_t)n << (n - 12)))) : 0;
     if (with_post) P.o_post = take((size_t)n * n * 8);
     if (with_post) P.o_ps = take((size_t)n * P.K * 8);
     if (with_data) P.o_data = take((size_t)n * (size_t)std::max(m, 1));
@@ -333,6 +337,7 @@ static LatticeArgs lattice_args(const Plan &P, char *ws, double *dev_post, doubl
     a.lin_mode = P.lin_mode;
     a.fbA = P.bA == 13 ? reinterpret_cast<uint32_t *>(ws + P.o_fbA) : nullptr;
     a.fbG = P.bG == 12 ? reinterpret_cast<uint32_t *>(ws + P.o_fbG) : nullptr;
+    a.rtG = P.bG == 12 ? reinterpret_cast<uint32_t *>(ws + P.o_rtG) : nullptr;
     a.betal = P.bA == 13 ? reinterpret_cast<double *>(ws + P.o_betal) : nullptr;
     a.anc = ws + P.o_anc;
     a.linok = reinterpret_cast<int *>(ws + P.o_linok);
