@@ -736,6 +736,8 @@ __host__ __device__ constexpr uint32_t colex4(uint32_t r) {
     return c;
 }
 
+__host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
 // Padded LDS index: one spare slot every 16 entries.
 __device__ inline uint32_t padx(uint32_t x) { return x + (x >> 4); }
 
@@ -1127,13 +1129,43 @@ k_alpha_small(int n, int d, uint32_t K, Tables tb, const typename P::V *__restri
 }
 
 // ------------------------------------------- a3/a4: sweep helpers
+// In-tile alpha slices in LDS. The FP32-scaled form keeps the stored form,
+// a plane of significands and a plane of exponent bytes (5 bytes per entry,
+// so more workgroups share a CU); the log form keeps the values.
+template <class P>
+struct SliceLds {
+    typename P::V *v;
+    __device__ SliceLds(void *base, uint32_t) : v(reinterpret_cast<typename P::V *>(base)) {}
+    __device__ typename P::V at(uint32_t k) const { return v[k]; }
+    __device__ void put4(uint32_t e, const typename P::Raw4 &r) { P::decode4_nz(r, v + e); }
+    __device__ void put(uint32_t e, const typename P::Store &s, uint64_t i) { v[e] = P::load(s, i); }
+    static constexpr size_t bytes_per_entry = sizeof(typename P::V);
+};
+template <>
+struct SliceLds<PolX32> {
+    float *f;
+    uint8_t *b;
+    __device__ SliceLds(void *base, uint32_t total)
+        : f(reinterpret_cast<float *>(base)), b(reinterpret_cast<uint8_t *>(f + total)) {}
+    // factor of a product only: a stored zero has significand 0
+    __device__ X32 at(uint32_t k) const { return X32{f[k], ((int)b[k] - kX32Bias) << 6}; }
+    __device__ void put4(uint32_t e, const PolX32::Raw4 &r) {
+        *reinterpret_cast<float4 *>(f + e) = r.f;
+        *reinterpret_cast<uint32_t *>(b + e) = r.b;
+    }
+    __device__ void put(uint32_t e, const PolX32::Store &s, uint64_t i) {
+        f[e] = s.f[i];
+        b[e] = s.b[i];
+    }
+    static constexpr size_t bytes_per_entry = 5;
+};
+
 // Stage alpha_i(Hf + Lo') (Lo' without bit i) for the bL tile bits into LDS:
 // slice i is the contiguous block alpha_i[(Hf >> 1) + k], k < 2^(bL-1).
-// All loads of a thread are issued before any is decoded.
+// All loads of a thread are issued before any is stored.
 template <class P>
 __device__ inline void stage_alpha(const typename P::Store &alpha, uint64_t NN, uint64_t Hf,
-                                   int bL, typename P::V *la) {
-    using V = typename P::V;
+                                   int bL, SliceLds<P> &la) {
     const uint32_t half = 1u << (bL - 1);
     const uint32_t total = (uint32_t)bL * half;
     const int t = threadIdx.x;
@@ -1151,12 +1183,12 @@ __device__ inline void stage_alpha(const typename P::Store &alpha, uint64_t NN, 
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t e = e0 + 4 * kThreads * u;
-                if (e < total) P::decode4_nz(raw[u], la + e);   // product factors only
+                if (e < total) la.put4(e, raw[u]);   // product factors only
             }
         }
     } else {
         for (uint32_t e = t; e < total; e += kThreads)
-            la[e] = P::load(alpha, (uint64_t)(e >> (bL - 1)) * NN + (Hf >> 1) + (e & (half - 1)));
+            la.put(e, alpha, (uint64_t)(e >> (bL - 1)) * NN + (Hf >> 1) + (e & (half - 1)));
     }
 }
 
@@ -1204,8 +1236,8 @@ k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
     extern __shared__ unsigned char smem[];
     const uint32_t half = 1u << (bL - 1);
     const uint32_t T = 1u << bL;
-    V *la = reinterpret_cast<V *>(smem);   // bL * half
-    V *lt = la + (size_t)bL * half;        // 2^bL
+    SliceLds<P> la(smem, (uint32_t)bL * half);   // bL * half entries
+    V *lt = reinterpret_cast<V *>(smem + align16(SliceLds<P>::bytes_per_entry * bL * half));
     uint16_t *lord = reinterpret_cast<uint16_t *>(lt + T);
     __shared__ uint32_t loff[34];
     __shared__ int pos[32];
@@ -1242,7 +1274,7 @@ k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
                 const int i = __ffs(rest) - 1;
                 rest &= rest - 1;
                 const uint32_t Tm = lo ^ (1u << i);
-                acc = P::add(acc, P::mul_raw(la[i * half + (uint32_t)compress_bit(Tm, i)], lt[Tm]));
+                acc = P::add(acc, P::mul_raw(la.at(i * half + (uint32_t)compress_bit(Tm, i)), lt[Tm]));
             }
             lt[lo] = P::norm_v(acc);
         }
@@ -1262,8 +1294,8 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
     extern __shared__ unsigned char smem[];
     const uint32_t half = 1u << (bL - 1);
     const uint32_t T = 1u << bL;
-    V *la = reinterpret_cast<V *>(smem);
-    V *lt = la + (size_t)bL * half;
+    SliceLds<P> la(smem, (uint32_t)bL * half);
+    V *lt = reinterpret_cast<V *>(smem + align16(SliceLds<P>::bytes_per_entry * bL * half));
     uint16_t *lord = reinterpret_cast<uint16_t *>(lt + T);
     __shared__ uint32_t loff[34];
     __shared__ int pos[32];
@@ -1310,7 +1342,7 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
             while (rest) {
                 const int i = __ffs(rest) - 1;
                 rest &= rest - 1;
-                acc = P::add(acc, P::mul_raw(la[i * half + (uint32_t)compress_bit(lo, i)],
+                acc = P::add(acc, P::mul_raw(la.at(i * half + (uint32_t)compress_bit(lo, i)),
                                              lt[lo | (1u << i)]));
             }
             lt[lo] = P::norm_v(acc);
@@ -2735,8 +2767,8 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     BN_CHECK_LAUNCH();
     rec(2);
     const int nh = n - a.bL;
-    const size_t smL = sizeof(V) * (((size_t)a.bL << (a.bL - 1)) + ((size_t)1 << a.bL)) +
-                       2 * ((size_t)1 << a.bL);
+    const size_t smL = align16(SliceLds<P>::bytes_per_entry * ((size_t)a.bL << (a.bL - 1))) +
+                       sizeof(V) * ((size_t)1 << a.bL) + 2 * ((size_t)1 << a.bL);
     for (int h = 0; h <= nh; ++h) {
         const unsigned nb = a.tiles_per_layer[h];
         hipLaunchKernelGGL(k_fwd<P>, dim3(nb), dim3(kThreads), smL, st, n, a.bL, h, tb, alpha, L,
