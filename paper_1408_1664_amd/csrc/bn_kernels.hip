@@ -2843,7 +2843,10 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
             BN_CHECK_LAUNCH();
         }
         if (gg.blkA[n] > 0) {
-            if (a.aG == 12)
+            // dense 12-bit form for the FP32-scaled system; the log form keeps the
+            // truncated pass (its log-adds are costly enough that the skipped
+            // entries matter more than the indexing)
+            if (a.aG == 12 && std::is_same<P, PolX32>::value)
                 hipLaunchKernelGGL(k_gamma_highA12<P>, dim3(gg.blkA[n]), dim3(kThreads),
                                    sizeof(V) * (4096 + 256), st, n, a.KA, gg, tb, (const V *)Y1,
                                    Y2);

@@ -106,9 +106,11 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     const int N = P.N, d = P.d;
     P.K = (uint32_t)kcount_u64(N, d);
     P.bA = N >= 13 ? 13 : N;      // alpha tile: 13 bits, or the whole lattice when smaller
-    // sweep tile: 9 bits for the large lattices (more workgroups per CU), 10
-    // below n = 23 (one launch fewer per sweep where launches dominate)
-    P.bL = std::min(n, n >= 23 ? 9 : 10);
+    // sweep tile: 9 bits for the large FP32-scaled lattices (more workgroups
+    // per CU for an HBM-bound sweep); 10 below n = 23 (one launch fewer per
+    // sweep where launches dominate) and for the log form, whose log-add
+    // cross terms want all 256 threads busy (4 entries each)
+    P.bL = std::min(n, (P.x32 && n >= 23) ? 9 : 10);
     P.bG = n >= 12 ? 12 : n;      // Gamma tile: 12 bits, or the whole lattice when smaller
     P.aG = 12;
     // Tuning / test override "bA,bL,bG,aG" (each clamped to its valid range);
