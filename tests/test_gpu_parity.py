@@ -313,3 +313,20 @@ def test_modular_feature_edges_and_sets_agree_with_solve(prec):
     lf[v, r0] = 0.0
     r = bn.modular_feature_posterior(ds.data, ds.arity, d, lf, precision=prec, ess=p["ess"])
     assert r["value"] == pytest.approx(ps[v, r0], abs=TOL[prec] * 10)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_modular_feature_custom_prior_and_k2(prec):
+    """A modular feature under a custom order-modular prior (log rho, log q)
+    and the K2 score, against the oracle."""
+    ds = datagen.random_dag_dataset(10, 400, 3, 3, 1.0, seed=12)
+    n, d = 10, 3
+    rng = np.random.default_rng(5)
+    log_rho = rng.normal(size=d + 1)
+    log_q = rng.normal(size=n) * 3
+    lf, full = _ranked_feature(n, d, rng, "weights")
+    logB = O.full_log_beta(ds.data, ds.arity, d, kind=O.K2, log_rho=log_rho)
+    ref = O.modular_feature_posterior(logB, d, full, log_q=log_q)
+    got = bn.modular_feature_posterior(ds.data, ds.arity, d, lf, precision=prec, score="k2",
+                                       log_rho=log_rho, log_q=log_q)
+    assert got["value"] == pytest.approx(ref["value"], rel=TOL[prec])
