@@ -39,6 +39,29 @@ struct PolLog {
     }
     __device__ static inline V mul_raw(V a, V b) { return a + b; }
     __device__ static inline V norm_v(V a) { return a; }
+    // Running sum of many terms: s * e^m, rescaled when a larger term comes
+    // in. One exp per term (add() takes an exp and a log1p); the log is
+    // taken once, by acc_value.
+    struct Acc {
+        double m, s;
+    };
+    __device__ static inline Acc acc_of(V x) {
+        return x > -1e300 ? Acc{x, 1.0} : Acc{-__builtin_huge_val(), 0.0};
+    }
+    __device__ static inline void acc_add(Acc &a, V t) {
+        if (!(t > -1e300)) return;
+        const double dlt = t - a.m;            // +inf while a is empty
+        const double e = exp(-fabs(dlt));
+        if (dlt > 0.0) {
+            a.s = a.s * e + 1.0;
+            a.m = t;
+        } else {
+            a.s += e;
+        }
+    }
+    __device__ static inline V acc_value(const Acc &a) {
+        return a.s > 0.0 ? a.m + log(a.s) : -__builtin_huge_val();
+    }
     // Undecoded HBM value: lets loads be issued long before their use.
     using Raw = double;
     __device__ static inline Raw load_raw(const Store &s, uint64_t i) { return s.p[i]; }
@@ -179,6 +202,11 @@ struct PolX32 {
         const int em = max(a.e, b.e);
         return X32{ldexpf(a.f, a.e - em) + ldexpf(b.f, b.e - em), em};
     }
+    // Running sum of many terms: the aligned add itself.
+    using Acc = X32;
+    __device__ static inline Acc acc_of(V x) { return x; }
+    __device__ static inline void acc_add(Acc &a, V t) { a = add(a, t); }
+    __device__ static inline V acc_value(const Acc &a) { return a; }
     __device__ static inline V from_log(double x) {
         if (!(x > -1e300)) return zero();
         const double t = x * 1.4426950408889634074;  // log2

@@ -1196,7 +1196,8 @@ __device__ inline void stage_alpha(const typename P::Store &alpha, uint64_t NN, 
 // four nodes per batch of loads.
 template <class P, class AI, class XI>
 __device__ inline void cross_terms(const typename P::Store &alpha, const typename P::Store &X,
-                                   const int *nodes, int cnt, AI ai, XI xi, typename P::V *acc) {
+                                   const int *nodes, int cnt, AI ai, XI xi,
+                                   typename P::Acc *acc) {
     using V = typename P::V;
     constexpr int B = 4;
     for (int q0 = 0; q0 < cnt; q0 += B) {
@@ -1216,7 +1217,7 @@ __device__ inline void cross_terms(const typename P::Store &alpha, const typenam
                 P::decode4_nz(ra[u], a);
                 P::decode4_nz(rx[u], x);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) acc[k] = P::add(acc[k], P::mul_raw(a[k], x[k]));
+                for (int k = 0; k < 4; ++k) P::acc_add(acc[k], P::mul_raw(a[k], x[k]));
             }
         }
     }
@@ -1255,28 +1256,28 @@ k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
     stage_alpha<P>(alpha, NN, Hf, bL, la);
     // cross-tile terms: alpha_i(S - i) L(S - i) for i in H
     for (uint32_t lo = 4 * t; lo < T; lo += 4 * kThreads) {
-        V acc[4];
+        typename P::Acc acc[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] = (Hf == 0 && lo + k == 0) ? P::one() : P::zero();
+        for (int k = 0; k < 4; ++k) acc[k] = P::acc_of((Hf == 0 && lo + k == 0) ? P::one() : P::zero());
         cross_terms<P>(alpha, L, pos, h,
                        [&](int i) { return (uint64_t)i * NN + compress_bit((Hf ^ (1ull << i)) | lo, i); },
                        [&](int i) { return (Hf ^ (1ull << i)) | lo; }, acc);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) lt[lo + k] = P::norm_v(acc[k]);
+        for (int k = 0; k < 4; ++k) lt[lo + k] = P::norm_v(P::acc_value(acc[k]));
     }
     __syncthreads();
     for (int l = 1; l <= bL; ++l) {
         for (uint32_t idx = loff[l] + t; idx < loff[l + 1]; idx += kThreads) {
             const uint32_t lo = lord[idx];
-            V acc = lt[lo];
+            typename P::Acc acc = P::acc_of(lt[lo]);
             uint32_t rest = lo;
             while (rest) {
                 const int i = __ffs(rest) - 1;
                 rest &= rest - 1;
                 const uint32_t Tm = lo ^ (1u << i);
-                acc = P::add(acc, P::mul_raw(la.at(i * half + (uint32_t)compress_bit(Tm, i)), lt[Tm]));
+                P::acc_add(acc, P::mul_raw(la.at(i * half + (uint32_t)compress_bit(Tm, i)), lt[Tm]));
             }
-            lt[lo] = P::norm_v(acc);
+            lt[lo] = P::norm_v(P::acc_value(acc));
         }
         __syncthreads();
     }
@@ -1322,30 +1323,30 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
     const uint64_t highall = ((1ull << nh) - 1) << bL;
     stage_alpha<P>(alpha, NN, Hf, bL, la);
     for (uint32_t lo = 4 * t; lo < T; lo += 4 * kThreads) {
-        V acc[4];
+        typename P::Acc acc[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            acc[k] = (Hf == highall && lo + k == T - 1) ? P::one() : P::zero();
+            acc[k] = P::acc_of((Hf == highall && lo + k == T - 1) ? P::one() : P::zero());
         const uint64_t Sm = Hf | lo;
         cross_terms<P>(alpha, R, outs, nout,
                        [&](int i) { return (uint64_t)i * NN + compress_bit(Sm, i); },
                        [&](int i) { return Sm | (1ull << i); }, acc);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) lt[lo + k] = P::norm_v(acc[k]);
+        for (int k = 0; k < 4; ++k) lt[lo + k] = P::norm_v(P::acc_value(acc[k]));
     }
     __syncthreads();
     for (int l = bL - 1; l >= 0; --l) {
         for (uint32_t idx = loff[l] + t; idx < loff[l + 1]; idx += kThreads) {
             const uint32_t lo = lord[idx];
-            V acc = lt[lo];
+            typename P::Acc acc = P::acc_of(lt[lo]);
             uint32_t rest = (T - 1) & ~lo;
             while (rest) {
                 const int i = __ffs(rest) - 1;
                 rest &= rest - 1;
-                acc = P::add(acc, P::mul_raw(la.at(i * half + (uint32_t)compress_bit(lo, i)),
-                                             lt[lo | (1u << i)]));
+                P::acc_add(acc, P::mul_raw(la.at(i * half + (uint32_t)compress_bit(lo, i)),
+                                           lt[lo | (1u << i)]));
             }
-            lt[lo] = P::norm_v(acc);
+            lt[lo] = P::norm_v(P::acc_value(acc));
         }
         __syncthreads();
     }
