@@ -2336,15 +2336,15 @@ k_gamma_highB(int n, int d, int a, uint32_t KA, uint32_t K, GammaGeom gg, Tables
         const uint32_t p = tb.pat[pi];
         if (__popc(p) + __popc(y) > tr) continue;
         const V *src = base + (((size_t)s * KA + pi) << hB);
-        V acc = P::zero();
+        typename P::Acc acc = P::acc_of(P::zero());
         const uint32_t free_bits = (ny - 1) & ~y;
         uint32_t sub = 0;   // all supersets y | sub, sub a submask of free_bits, ascending
         while (true) {
-            acc = P::add(acc, src[y | sub]);
+            P::acc_add(acc, src[y | sub]);
             if (sub == free_bits) break;
             sub = (sub - free_bits) & free_bits;
         }
-        gam[(size_t)v * K + out_rank(bn, N, sigma, cl, p | (y << a), bv)] = acc;
+        gam[(size_t)v * K + out_rank(bn, N, sigma, cl, p | (y << a), bv)] = P::acc_value(acc);
     }
 }
 
@@ -2377,12 +2377,12 @@ k_edges(int n, uint32_t K, const uint32_t *__restrict__ famask,
             continue;
         }
         const int pu = u < v ? u : u - 1;
-        V acc = P::zero();
+        typename P::Acc acc = P::acc_of(P::zero());
         for (uint32_t r = t; r < K; r += kThreads) {
             if (u >= 0 && !((famask[r] >> pu) & 1)) continue;
-            acc = P::add(acc, P::mul(beta[(size_t)v * K + r], gam[(size_t)v * K + r]));
+            P::acc_add(acc, P::mul(beta[(size_t)v * K + r], gam[(size_t)v * K + r]));
         }
-        V tot = block_reduce(acc, red, add);
+        V tot = block_reduce(P::acc_value(acc), red, add);
         if (t == 0) {
             double lr = P::log_ratio(tot, LV);
             if (u < 0) resid[v] = fabs(lr);
