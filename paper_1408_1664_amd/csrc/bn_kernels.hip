@@ -2349,8 +2349,10 @@ k_gamma_highB(int n, int d, int a, uint32_t KA, uint32_t K, GammaGeom gg, Tables
 }
 
 // ------------------------------------------------------------ a7: edges
-// Workgroup v: w_v(G) = beta_v(G) Gamma_v(G); P(u->v) = sum_{G containing u}
-// w_v(G) / L(V), the last division in FP64. Also sum_G w_v(G) against L(V).
+// Workgroup (v, j): w_v(G) = beta_v(G) Gamma_v(G). j = 0: sum_G w_v(G)
+// against L(V) (the residual) and, when asked for, the parent-set
+// posteriors w_v(G) / L(V); j = u + 1: P(u->v) = sum_{G containing u}
+// w_v(G) / L(V), the last division in FP64.
 template <class P>
 __global__ void __launch_bounds__(kThreads)
 k_edges(int n, uint32_t K, const uint32_t *__restrict__ famask,
@@ -2360,34 +2362,33 @@ k_edges(int n, uint32_t K, const uint32_t *__restrict__ famask,
     using V = typename P::V;
     __shared__ V red[kThreads];
     const int v = blockIdx.x;
+    const int u = (int)blockIdx.y - 1;
     const int t = threadIdx.x;
+    if (u == v) {
+        if (t == 0) post[(size_t)u * n + v] = 0.0;
+        return;
+    }
     const V LV = P::load(L, (1ull << n) - 1);
     auto add = [](V a, V b) { return P::add(a, b); };
     // parent-set posteriors P(G_v = G | D) = w_v(G) / L(V), when asked for
-    if (ps) {
+    if (ps && u < 0) {
         for (uint32_t r = t; r < K; r += kThreads) {
             const double lr =
                 P::log_ratio(P::mul(beta[(size_t)v * K + r], gam[(size_t)v * K + r]), LV);
             ps[(size_t)v * K + r] = (lr > -1e300) ? exp(lr) : 0.0;
         }
     }
-    for (int u = -1; u < n; ++u) {
-        if (u == v) {
-            if (t == 0) post[(size_t)u * n + v] = 0.0;
-            continue;
-        }
-        const int pu = u < v ? u : u - 1;
-        typename P::Acc acc = P::acc_of(P::zero());
-        for (uint32_t r = t; r < K; r += kThreads) {
-            if (u >= 0 && !((famask[r] >> pu) & 1)) continue;
-            P::acc_add(acc, P::mul(beta[(size_t)v * K + r], gam[(size_t)v * K + r]));
-        }
-        V tot = block_reduce(P::acc_value(acc), red, add);
-        if (t == 0) {
-            double lr = P::log_ratio(tot, LV);
-            if (u < 0) resid[v] = fabs(lr);
-            else post[(size_t)u * n + v] = (lr > -1e300) ? exp(lr) : 0.0;
-        }
+    const int pu = u < v ? u : u - 1;
+    typename P::Acc acc = P::acc_of(P::zero());
+    for (uint32_t r = t; r < K; r += kThreads) {
+        if (u >= 0 && !((famask[r] >> pu) & 1)) continue;
+        P::acc_add(acc, P::mul(beta[(size_t)v * K + r], gam[(size_t)v * K + r]));
+    }
+    const V tot = block_reduce(P::acc_value(acc), red, add);
+    if (t == 0) {
+        const double lr = P::log_ratio(tot, LV);
+        if (u < 0) resid[v] = fabs(lr);
+        else post[(size_t)u * n + v] = (lr > -1e300) ? exp(lr) : 0.0;
     }
 }
 
@@ -2549,17 +2550,30 @@ __device__ inline void count_cells2(const uint32_t *__restrict__ bits, int W, in
         for (int sft = 8; sft > 0; sft >>= 1) cnt[c] += __shfl_xor(cnt[c], sft, 16);
 }
 
+// Log-gamma tables of the binary score path: for k = 0..4 parents,
+// lgt[(2k) * (m+1) + c] = lgamma(a_j + c) and lgt[(2k+1) * (m+1) + c] =
+// lgamma(a_jk + c), c = 0..m, with the hyperparameters of family_score2.
+__global__ void k_lgamma_table(int m, int kind, double ess, double *__restrict__ lgt) {
+    const int m1 = m + 1;
+    for (int x = blockIdx.x * kThreads + threadIdx.x; x < 10 * m1; x += gridDim.x * kThreads) {
+        const int row = x / m1, c = x - row * m1, k = row >> 1;
+        const double q = (double)(1 << k);
+        const double a = (row & 1) ? (kind == 0 ? ess / (2.0 * q) : 1.0)
+                                   : (kind == 0 ? ess / q : 2.0);
+        lgt[x] = lgamma(a + c);
+    }
+}
+
 // BDeu / K2 log marginal likelihood of one family from its cell counts
 // (all variables binary: q = 2^k configurations, r = 2 values); the
 // configurations are split over the 16 lanes, partial sums met by a fixed
-// butterfly.
+// butterfly. The log-gamma values come from the tables of k_lgamma_table.
 template <int KP>
-__device__ inline double family_score2(const uint32_t *cnt, int lane, int kind, double ess) {
+__device__ inline double family_score2(const uint32_t *cnt, int lane, const double *lgt,
+                                       int m1) {
     constexpr int Q = 1 << KP;
-    const double q = (double)Q;
-    const double a_j = kind == 0 ? ess / q : 2.0;
-    const double a_jk = kind == 0 ? ess / (2.0 * q) : 1.0;
-    const double lg_aj = lgamma(a_j), lg_ajk = lgamma(a_jk);
+    const double *lj = lgt + (2 * KP) * m1, *ljk = lgt + (2 * KP + 1) * m1;
+    const double lg_aj = lj[0], lg_ajk = ljk[0];
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
@@ -2567,9 +2581,9 @@ __device__ inline double family_score2(const uint32_t *cnt, int lane, int kind, 
         const uint32_t c0 = cnt[2 * j], c1 = cnt[2 * j + 1];
         const uint32_t nj = c0 + c1;
         if (nj) {
-            double s = lg_aj - lgamma(a_j + nj);
-            if (c0) s += lgamma(a_jk + c0) - lg_ajk;
-            if (c1) s += lgamma(a_jk + c1) - lg_ajk;
+            double s = lg_aj - lj[nj];
+            if (c0) s += ljk[c0] - lg_ajk;
+            if (c1) s += ljk[c1] - lg_ajk;
             acc += s;
         }
     }
@@ -2580,8 +2594,9 @@ __device__ inline double family_score2(const uint32_t *cnt, int lane, int kind, 
 // Local scores of all-binary data with d <= 4: 16 lanes per family, 16
 // families per workgroup, counts from the bit planes of k_pack2.
 __global__ void __launch_bounds__(kThreads)
-k_scores2(int n, int W, uint32_t K, int kind, double ess, const uint32_t *__restrict__ famask,
-          const uint32_t *__restrict__ bits, double *__restrict__ out) {
+k_scores2(int n, int W, int m, uint32_t K, const uint32_t *__restrict__ famask,
+          const uint32_t *__restrict__ bits, const double *__restrict__ lgt,
+          double *__restrict__ out) {
     const int g = threadIdx.x >> 4, lane = threadIdx.x & 15;
     const uint32_t fam = blockIdx.x * 16 + g;
     if (fam >= (uint32_t)n * K) return;      // whole 16-lane groups leave together
@@ -2595,11 +2610,11 @@ k_scores2(int n, int W, uint32_t K, int kind, double ess, const uint32_t *__rest
     uint32_t cnt[32];
     double sc = 0.0;
     switch (k) {
-        case 0: count_cells2<0>(bits, W, lane, i, par, cnt); sc = family_score2<0>(cnt, lane, kind, ess); break;
-        case 1: count_cells2<1>(bits, W, lane, i, par, cnt); sc = family_score2<1>(cnt, lane, kind, ess); break;
-        case 2: count_cells2<2>(bits, W, lane, i, par, cnt); sc = family_score2<2>(cnt, lane, kind, ess); break;
-        case 3: count_cells2<3>(bits, W, lane, i, par, cnt); sc = family_score2<3>(cnt, lane, kind, ess); break;
-        default: count_cells2<4>(bits, W, lane, i, par, cnt); sc = family_score2<4>(cnt, lane, kind, ess); break;
+        case 0: count_cells2<0>(bits, W, lane, i, par, cnt); sc = family_score2<0>(cnt, lane, lgt, m + 1); break;
+        case 1: count_cells2<1>(bits, W, lane, i, par, cnt); sc = family_score2<1>(cnt, lane, lgt, m + 1); break;
+        case 2: count_cells2<2>(bits, W, lane, i, par, cnt); sc = family_score2<2>(cnt, lane, lgt, m + 1); break;
+        case 3: count_cells2<3>(bits, W, lane, i, par, cnt); sc = family_score2<3>(cnt, lane, lgt, m + 1); break;
+        default: count_cells2<4>(bits, W, lane, i, par, cnt); sc = family_score2<4>(cnt, lane, lgt, m + 1); break;
     }
     if (lane == 0) out[fam] = sc;
 }
@@ -2659,8 +2674,12 @@ hipError_t launch_scores(int n, int m, const uint8_t *data, const uint8_t *arity
         hipLaunchKernelGGL(k_pack2, dim3((unsigned)((n * W + kThreads - 1) / kThreads)),
                            dim3(kThreads), 0, st, n, m, W, data, bits);
         BN_CHECK_LAUNCH();
+        double *lgt = reinterpret_cast<double *>(bits + (size_t)2 * n * W);
+        hipLaunchKernelGGL(k_lgamma_table, dim3((unsigned)std::min((10 * (m + 1) + kThreads - 1) / kThreads, 1024)),
+                           dim3(kThreads), 0, st, m, kind, ess, lgt);
+        BN_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_scores2, dim3((unsigned)((n * K + 15) / 16)), dim3(kThreads), 0, st,
-                           n, W, K, kind, ess, famask, (const uint32_t *)bits, out);
+                           n, W, m, K, famask, (const uint32_t *)bits, (const double *)lgt, out);
         BN_CHECK_LAUNCH();
         return hipSuccess;
     }
@@ -2862,7 +2881,7 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
         }
     }
     rec(5);
-    hipLaunchKernelGGL(k_edges<P>, dim3(n), dim3(kThreads), 0, st, n, a.K,
+    hipLaunchKernelGGL(k_edges<P>, dim3(n, n + 1), dim3(kThreads), 0, st, n, a.K,
                        (const uint32_t *)tb.famask, (const V *)beta, (const V *)gam, L, a.post,
                        a.resid, a.ps);
     BN_CHECK_LAUNCH();

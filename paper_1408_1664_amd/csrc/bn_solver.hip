@@ -192,7 +192,8 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.o_qt = take(32 * V);
     P.o_gexp = take(64 * 8);
     P.o_logp = take((size_t)n * P.K * 8);
-    P.o_bits = take((size_t)2 * n * ((std::max(m, 1) + 31) / 32) * 4);   // binary bit planes
+    // binary bit planes, then log-gamma tables (10 x (m + 1) doubles)
+    P.o_bits = take((size_t)2 * n * ((std::max(m, 1) + 31) / 32) * 4 + (size_t)10 * (m + 1) * 8);
     // everything the local-score step touches lies below this offset
     P.o_scores_end = o;
     P.o_beta = take((size_t)n * P.K * V);
