@@ -1001,7 +1001,8 @@ __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__
     __syncthreads();
 }
 
-// Linear-tile form of k_alpha. Workgroup (i, H) = the same 13-bit tile, run
+// Linear-tile form of k_alpha. A workgroup takes 2^tl consecutive tiles (i, H)
+// of one node in turn, each the same 13-bit tile as k_alpha's, run
 // as two 12-bit halves x = hb * 4096 + y through one half-size LDS buffer,
 // which lets four workgroups share a CU. The zeta step over tile bit 12 is
 // taken first: the upper half starts from its seeds plus the lower half's.
@@ -1018,7 +1019,7 @@ __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__
 // Four workgroups per CU (LDS allows it): registers are capped to match.
 template <class P>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
-k_alpha_lin(int n, int d, uint32_t KS, int force_fb, const double *__restrict__ Zs,
+k_alpha_lin(int n, int d, uint32_t KS, int force_fb, int tl, const double *__restrict__ Zs,
             const double *__restrict__ betal, uint32_t K, uint32_t offd,
             const typename P::Anchor *__restrict__ anc, const int *__restrict__ linok,
             const typename P::V *__restrict__ qt, typename P::Store alpha,
@@ -1036,11 +1037,11 @@ k_alpha_lin(int n, int d, uint32_t KS, int force_fb, const double *__restrict__ 
     __shared__ uint32_t k13[15];          // K(13, k - 1) = sum_{j < k} C(13, j)
     const int N = n - 1;
     const int hA = N - bA;
-    const int i = blockIdx.x >> hA;
-    const uint32_t H = blockIdx.x & ((1u << hA) - 1);
+    const uint32_t tile0 = blockIdx.x << tl;   // 2^tl consecutive tiles of one node
+    const int i = tile0 >> hA;
     const int t = threadIdx.x;
     if (force_fb || !linok[i]) {
-        if (t == 0) fb_push(fb, blockIdx.x);
+        if (t < (1 << tl)) fb_push(fb, tile0 + t);
         return;
     }
     const A T = anc[i];
@@ -1062,12 +1063,9 @@ k_alpha_lin(int n, int d, uint32_t KS, int force_fb, const double *__restrict__ 
         ord8[r] = (uint8_t)t;
     }
     __syncthreads();
-    const int h = __popc(H);
-    const double *zs = Zs + (size_t)blockIdx.x * KS;
     // size-d seeds: betal_i(G_L) at rank offd + colex(G_L), offd = K(N, d - 1);
     // indexed like zs (k13[d] + colex), so the base is shifted by k13[d]
     const double *zd = betal + (size_t)i * K + offd - k13[min(d, 14)];
-    const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
     const uint32_t pt = ord8[t];
     // colex contribution of pt's bits (tile bits 4..11), and of bit 12 in the
     // upper half, by the number m of set bits below them (both halves)
@@ -1086,9 +1084,15 @@ k_alpha_lin(int n, int d, uint32_t KS, int force_fb, const double *__restrict__ 
 #pragma unroll
         for (int m = 0; m < 5; ++m) cpt[m] = cup[m] = 0;
     }
-    alpha_lin_half<P, 0>(d, zs, zd, sq, cpt, cup, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
-    alpha_lin_half<P, 1>(d, zs, zd, sq, cpt, cup, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
-
+    for (int j = 0; j < (1 << tl); ++j) {
+        const uint32_t tile = tile0 + j;
+        const uint32_t H = tile & ((1u << hA) - 1);
+        const int h = __popc(H);
+        const double *zs = Zs + (size_t)tile * KS;
+        const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
+        alpha_lin_half<P, 0>(d, zs, zd, sq, cpt, cup, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
+        alpha_lin_half<P, 1>(d, zs, zd, sq, cpt, cup, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
+    }
 }
 
 // Generic form for lattices smaller than the 13-bit tile (n - 1 < 13): one
@@ -2755,8 +2759,12 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
             const size_t smL = 8 * (4096 + 256);
             allow_big_lds<k_alpha_lin<P>>();
             rec(8);
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_lin<P>), dim3(nblkA), dim3(kThreads), smL,
-                               st, n, d, a.KS, a.lin_mode == 2 ? 1 : 0, (const double *)a.Zs,
+            // 2^tl tiles per workgroup share its set-up (tables in LDS, the
+            // colex terms of the thread's pattern)
+            int tl = 0;
+            while (tl < 6 && ((uint64_t)n << (hA - tl - 1)) >= 4096) ++tl;
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_lin<P>), dim3(nblkA >> tl), dim3(kThreads), smL,
+                               st, n, d, a.KS, a.lin_mode == 2 ? 1 : 0, tl, (const double *)a.Zs,
                                (const double *)a.betal, a.K,
                                host_kcount(N, d - 1), (const A *)a.anc, (const int *)a.linok, (const V *)qt, alpha,
                                a.cnt, a.fbA);
