@@ -36,10 +36,46 @@ __device__ inline T block_reduce(T v, T *scratch, Op op) {
 }
 
 // ------------------------------------------------------------------ setup
+// Lane order of the Gamma tile's layout C, where lane t holds the 8-bit
+// pattern p = ordC[t] of tile bits 4..11 and reads its 16 doubles at padded
+// slots r * 272 + p + p / 16. The patterns with at most d ones fill the first
+// 2 * ceil(nlive / 64) groups of 32 lanes (so the same number of waves holds
+// them as in popcount order), each going to the group with room where the
+// fewest patterns already share its bank pair (p + p / 16) mod 32; the other
+// patterns fill the remaining lanes. Computed once per d on the host.
+struct LaneOrder {
+    uint8_t p[256];
+};
+
+static LaneOrder lane_order_c(int d) {
+    LaneOrder o{};
+    int cntb[8][32] = {}, fill[8] = {};
+    int nl = 0;
+    for (int p = 0; p < 256; ++p) nl += __builtin_popcount(p) <= d ? 1 : 0;
+    const int ng = std::min(8, 2 * ((nl + 63) / 64));
+    for (int k = 0; k <= 8; ++k) {
+        for (int p = 0; p < 256; ++p) {
+            if (__builtin_popcount(p) != k) continue;
+            int best = -1;
+            if (k <= d) {
+                const int f = (p + (p >> 4)) & 31;
+                for (int g = 0; g < ng; ++g)
+                    if (fill[g] < 32 && (best < 0 || cntb[g][f] < cntb[best][f])) best = g;
+                ++cntb[best][f];
+            } else {
+                best = 0;
+                while (fill[best] == 32) ++best;
+            }
+            o.p[best * 32 + fill[best]++] = (uint8_t)p;
+        }
+    }
+    return o;
+}
+
 // Tables: binomials, popcount-ordered masks of the sweep tile, patterns of
 // at most d ones (numeric order: the w-bit patterns are exactly the first
 // K(w,d) entries), and the ranked seed masks of the Gamma tile.
-__global__ void k_setup(Tables tb, int bL, int W, int bG, int d) {
+__global__ void k_setup(Tables tb, LaneOrder oc, int bL, int W, int bG, int d) {
     const int t = threadIdx.x;
     if (t == 0) {
         for (int a = 0; a <= 32; ++a)
@@ -82,6 +118,8 @@ __global__ void k_setup(Tables tb, int bL, int W, int bG, int d) {
         }
         tb.pat[pos] = (uint16_t)x;
     }
+    // lane order of the Gamma tile's layout C (lane_order_c)
+    tb.ordC[t] = oc.p[t];
     // ranked seed masks of the Gamma tile (bG bits): size, then colex
     for (uint32_t x = t; x < (1u << bG); x += kThreads) {
         int k = __popc(x);
@@ -1637,7 +1675,6 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
     __shared__ A sT[32];
     __shared__ int sok[32];
     __shared__ int sfail;
-    __shared__ uint8_t ord8[256];
     const int t = threadIdx.x;
     const int hbits = n - bT;
     const uint32_t nblk = 1u << hbits;
@@ -1670,14 +1707,6 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
         }
 #pragma unroll
         for (int k = 0; k < 5; ++k) gv[t * 5 + k] = lr[k];
-        {   // ord8: 8-bit patterns by popcount (then value)
-            const int k = __popc(t);
-            uint32_t r = Kcount(sbin, 8, k - 1);
-            int j = 0;
-            for (int p = 0; p < 8; ++p)
-                if ((t >> p) & 1) r += C(sbin, p, ++j);
-            ord8[r] = (uint8_t)t;
-        }
         __syncthreads();
         {   // layer l = t / 16 of the tile: 16 lanes x 16 slots, then a lane tree
             const int l = t >> 4, j = t & 15;
@@ -1727,7 +1756,7 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
         for (int r = 0; r < NR; ++r) qL[r] = P::mul_raw(qa[__builtin_popcount(r)], P::at16_nz(Lw, r));
     }
     const uint32_t tlo = t & 15, thi = t >> 4;
-    const uint32_t pc = ord8[t];
+    const uint32_t pc = tb.ordC[t];
     const bool liveC = __popc(pc) <= d;
     for (int v = 0; v < n; ++v) {
         const bool low = v < bT;
@@ -2654,7 +2683,14 @@ static void allow_big_lds() {
 
 hipError_t launch_setup(const Tables &tb, int bL, int W, int bG, int bA, int d, uint32_t N,
                         uint32_t K, hipStream_t st) {
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(kThreads), 0, st, tb, bL, W, bG, d);
+    static const struct OrdTable {
+        LaneOrder o[9];
+        OrdTable() {
+            for (int d = 0; d <= 8; ++d) o[d] = lane_order_c(d);
+        }
+    } ord_tables;
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(kThreads), 0, st, tb, ord_tables.o[std::min(std::max(d, 0), 8)],
+                       bL, W, bG, d);
     BN_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_ranked, dim3(((1u << bA) + kThreads - 1) / kThreads), dim3(kThreads),
                        0, st, (const uint32_t *)tb.binom, bA, d, tb.seedA);

@@ -27,7 +27,7 @@ struct Plan {
     GammaGeom gg;                 // per-endpoint Gamma geometry
     uint64_t y1_elems, y2_elems;
     std::vector<uint32_t> tiles;  // C(n - bL, h), h = 0..n-bL
-    size_t o_binom, o_lorder, o_loff, o_pat, o_seed, o_famask, o_seedA, o_items, o_arity, o_rho, o_q, o_logp,
+    size_t o_binom, o_lorder, o_loff, o_pat, o_seed, o_famask, o_seedA, o_items, o_ordC, o_arity, o_rho, o_q, o_logp,
         o_beta, o_qt, o_gexp, o_alpha_f, o_alpha_b, o_L_f, o_L_b, o_R_f, o_R_b, o_Y1, o_Y2,
         o_gam, o_part, o_layer, o_resid, o_diag, o_cnt, o_post, o_data, o_scores_end, o_fbA,
         o_fbG, o_rtG, o_betal, o_anc, o_linok, o_Zs, o_ps, o_bits;

@@ -182,6 +182,7 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.o_famask = take((size_t)P.K * 4);
     P.o_seedA = take(kcount_u64(P.bA, d) * 4);
     P.o_items = take(kcount_u64(N - P.bA, d) * 4);
+    P.o_ordC = take(256);
     P.o_arity = take(64);
     P.o_rho = take(34 * 8);
     P.o_q = take(32 * 8);
@@ -262,6 +263,7 @@ static Tables tables_of(const Plan &P, char *ws) {
     tb.famask = reinterpret_cast<uint32_t *>(ws + P.o_famask);
     tb.seedA = reinterpret_cast<uint32_t *>(ws + P.o_seedA);
     tb.items = reinterpret_cast<uint32_t *>(ws + P.o_items);
+    tb.ordC = reinterpret_cast<uint8_t *>(ws + P.o_ordC);
     return tb;
 }
 
