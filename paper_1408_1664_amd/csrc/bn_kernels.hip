@@ -37,7 +37,7 @@ __device__ inline T block_reduce(T v, T *scratch, Op op) {
 
 // ------------------------------------------------------------------ setup
 // Lane order of the Gamma tile's layout C, where lane t holds the 8-bit
-// pattern p = ordC[t] of tile bits 4..11 and reads its 16 doubles at padded
+// pattern p = ordC[t] of tile bits 0..7 and reads its 16 doubles at padded
 // slots r * 272 + p + p / 16. The patterns with at most d ones fill the first
 // 2 * ceil(nlive / 64) groups of 32 lanes (so the same number of waves holds
 // them as in popcount order), each going to the group with room where the
