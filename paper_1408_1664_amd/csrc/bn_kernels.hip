@@ -77,12 +77,14 @@ static LaneOrder lane_order_c(int d) {
 // K(w,d) entries), and the ranked seed masks of the Gamma tile.
 __global__ void k_setup(Tables tb, LaneOrder oc, int bL, int W, int bG, int d) {
     const int t = threadIdx.x;
-    if (t == 0) {
-        for (int a = 0; a <= 32; ++a)
-            for (int b = 0; b <= 32; ++b)
-                tb.binom[a * 33 + b] =
-                    (b == 0) ? 1u : (a == 0 ? 0u : tb.binom[(a - 1) * 33 + b - 1] +
-                                                        (b <= a - 1 ? tb.binom[(a - 1) * 33 + b] : 0u));
+    // C(a, b) by the product formula, one entry per thread: after step j the
+    // running value is C(a - b + j, j), so every division is exact and no
+    // intermediate exceeds 32 * C(32, 16) < 2^35
+    for (int x = t; x < 33 * 33; x += kThreads) {
+        const int a = x / 33, b = x % 33;
+        uint64_t c = b <= a ? 1u : 0u;
+        for (int j = 1; j <= b && b <= a; ++j) c = c * (uint64_t)(a - b + j) / (uint64_t)j;
+        tb.binom[x] = (uint32_t)c;
     }
     __syncthreads();
     const uint32_t *bn = tb.binom;
