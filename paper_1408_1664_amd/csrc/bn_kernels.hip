@@ -910,8 +910,8 @@ k_alpha_seeds_blk(int n, int d, uint32_t K, uint32_t KS, int b, uint32_t nhiMax,
 template <class P, int hb>
 __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__ zs,
                                                const double *__restrict__ zd,
-                                               const typename P::V *sq, const uint32_t *cpt,
-                                               const uint32_t *cup,
+                                               const typename P::V *sq, const uint16_t *ctab,
+                                               const uint16_t *cb,
                                                const uint32_t *k13, uint32_t *tlo_,
                                                uint32_t *thi_, uint32_t pt, int h,
                                                uint64_t base, typename P::Anchor T,
@@ -928,11 +928,15 @@ __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__
     //      from its own seeds plus the lower half's (the zeta step over
     //      tile bit 12 commutes with the others).
     if (__any(kp <= d)) {
-        uint32_t off[5], offu[5];
+        // colex terms of pt's bits (tile bits 4..11) with m ones below them,
+        // and of bit 12 on top for the upper half's second seed
+        uint32_t off[5], offu[5], cpt[5], cup[5];
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
             off[m] = k13[min(kp + m, 14)];
             offu[m] = k13[min(kp + m + 1, 14)];
+            cpt[m] = ctab[m * 256 + pt];
+            cup[m] = cpt[m] + cb[12 * 14 + min(kp + m + 1, 13)];
         }
         // every load is issued (clamped to a valid index of zd) before any is
         // used; seeds of size d come from zd, smaller ones from zs
@@ -1075,6 +1079,10 @@ k_alpha_lin(int n, int d, uint32_t KS, int force_fb, int tl, const double *__res
     __shared__ uint8_t ord8[256];
     __shared__ uint16_t cb[14 * 14];      // C(a, b), a, b <= 13
     __shared__ uint32_t k13[15];          // K(13, k - 1) = sum_{j < k} C(13, j)
+    // ctab[m * 256 + p]: colex terms of the 8-bit pattern p at tile bits
+    // 4..11 with m ones below it (kept in LDS rather than in registers
+    // across the tile loop)
+    __shared__ uint16_t ctab[5 * 256];
     const int N = n - 1;
     const int hA = N - bA;
     const uint32_t tile0 = blockIdx.x << tl;   // 2^tl consecutive tiles of one node
@@ -1102,36 +1110,27 @@ k_alpha_lin(int n, int d, uint32_t KS, int force_fb, int tl, const double *__res
             if ((t >> p) & 1) r += cb[p * 14 + (++j)];
         ord8[r] = (uint8_t)t;
     }
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+        uint32_t c = 0;
+        int j = m;
+        for (int p = 0; p < 8; ++p)
+            if ((t >> p) & 1) c += cb[(4 + p) * 14 + (++j)];
+        ctab[m * 256 + t] = (uint16_t)c;
+    }
     __syncthreads();
     // size-d seeds: betal_i(G_L) at rank offd + colex(G_L), offd = K(N, d - 1);
     // indexed like zs (k13[d] + colex), so the base is shifted by k13[d]
     const double *zd = betal + (size_t)i * K + offd - k13[min(d, 14)];
     const uint32_t pt = ord8[t];
-    // colex contribution of pt's bits (tile bits 4..11), and of bit 12 in the
-    // upper half, by the number m of set bits below them (both halves)
-    uint32_t cpt[5], cup[5];
-    if (__popc(pt) <= d) {
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {
-            uint32_t c = 0;
-            int j = m;
-            for (int p = 0; p < 8; ++p)
-                if ((pt >> p) & 1) c += (4 + p >= ++j) ? cb[(4 + p) * 14 + j] : 0u;
-            cpt[m] = c;
-            cup[m] = c + ((12 >= j + 1) ? cb[12 * 14 + j + 1] : 0u);
-        }
-    } else {
-#pragma unroll
-        for (int m = 0; m < 5; ++m) cpt[m] = cup[m] = 0;
-    }
     for (int j = 0; j < (1 << tl); ++j) {
         const uint32_t tile = tile0 + j;
         const uint32_t H = tile & ((1u << hA) - 1);
         const int h = __popc(H);
         const double *zs = Zs + (size_t)tile * KS;
         const uint64_t base = ((uint64_t)i << N) | ((uint64_t)H << bA);
-        alpha_lin_half<P, 0>(d, zs, zd, sq, cpt, cup, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
-        alpha_lin_half<P, 1>(d, zs, zd, sq, cpt, cup, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
+        alpha_lin_half<P, 0>(d, zs, zd, sq, ctab, cb, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
+        alpha_lin_half<P, 1>(d, zs, zd, sq, ctab, cb, k13, tlo_, thi_, pt, h, base, T, alpha, cnt);
     }
 }
 
