@@ -923,6 +923,12 @@ __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__
     const int kp = __popc(pt);
     const uint32_t tlo = t & 15, thi = t >> 4;
     const int kh = __popc(thi);
+    // pad16 indices written as a lane base plus a constant per register, so
+    // that the constants fold into the LDS offsets:
+    //   A: pad16(pt * 16 + r) = 17 pt + r,
+    //   B: pad16(thi * 256 + r * 16 + tlo) = 272 thi + tlo + 17 r,
+    //   C: pad16(r * 256 + t) = t + t / 16 + 272 r
+    const uint32_t ib = thi * 272 + tlo, ic = t + (t >> 4);
     double v[NR];
     // ---- layout A: y = pt * 16 + r, tile bits 0..3. The upper half starts
     //      from its own seeds plus the lower half's (the zeta step over
@@ -960,13 +966,13 @@ __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__
         for (int q = 0; q < 4; ++q) lin_zeta_up<NR>(v, q);
         if (kp <= d) {
 #pragma unroll
-            for (int r = 0; r < NR; ++r) put_w2(tlo_, thi_, pad16((pt << 4) | r), v[r]);
+            for (int r = 0; r < NR; ++r) put_w2(tlo_, thi_, pt * 17 + r, v[r]);
         }
     }
     __syncthreads();
     // ---- layout B: y = thi * 256 + r * 16 + tlo, tile bits 4..7
 #pragma unroll
-    for (int r = 0; r < NR; ++r) v[r] = get_w2(tlo_, thi_, pad16((thi << 8) | (r << 4) | tlo));
+    for (int r = 0; r < NR; ++r) v[r] = get_w2(tlo_, thi_, ib + r * 17);
 #pragma unroll
     for (int r = 0; r < NR; ++r)
         if (kh + __builtin_popcount(r) > d) v[r] = 0.0;      // slot never written
@@ -974,11 +980,11 @@ __device__ __forceinline__ void alpha_lin_half(int d, const double *__restrict__
     for (int q = 0; q < 4; ++q) lin_zeta_up<NR>(v, q);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < NR; ++r) put_w2(tlo_, thi_, pad16((thi << 8) | (r << 4) | tlo), v[r]);
+    for (int r = 0; r < NR; ++r) put_w2(tlo_, thi_, ib + r * 17, v[r]);
     __syncthreads();
     // ---- layout C: y = r * 256 + t, tile bits 8..11
 #pragma unroll
-    for (int r = 0; r < NR; ++r) v[r] = get_w2(tlo_, thi_, pad16(r * kThreads + t));
+    for (int r = 0; r < NR; ++r) v[r] = get_w2(tlo_, thi_, ic + r * 272);
 #pragma unroll
     for (int q = 0; q < 4; ++q) lin_zeta_up<NR>(v, q);
     // ---- alpha = q(|S|) t(S), |S| = h + hb + |t| + |r|
@@ -1759,6 +1765,13 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
     const uint32_t tlo = t & 15, thi = t >> 4;
     const uint32_t pc = tb.ordC[t];
     const bool liveC = __popc(pc) <= d;
+    // padx indices as a lane base plus a constant per register (folded into
+    // the LDS offsets): A, padx(t * 16 + r) = 17 t + r; B, padx(thi * 256 +
+    // r * 16 + tlo) = 272 thi + tlo + 17 r; C, padx(r * 256 + pc) =
+    // pc + pc / 16 + 272 r. The log form takes these (no spills then); the
+    // FP32-scaled form measured faster with the plain padx indices.
+    const uint32_t iA = 17 * t, iB = 272 * thi + tlo, iC = pc + (pc >> 4);
+    constexpr bool kFold = !std::is_same<P, PolX32>::value;
     for (int v = 0; v < n; ++v) {
         const bool low = v < bT;
         if (!low && ((Hf >> v) & 1)) continue;
@@ -1801,26 +1814,26 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
             if (v != q) lin_zeta_down<NR>(g, q);
         // ---- A -> B, tile bits 4..7
 #pragma unroll
-        for (int r = 0; r < NR; ++r) gb[padx((t << 4) | r)] = g[r];
+        for (int r = 0; r < NR; ++r) gb[kFold ? iA + r : padx((t << 4) | r)] = g[r];
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < NR; ++r) g[r] = gb[padx((thi << 8) | (r << 4) | tlo)];
+        for (int r = 0; r < NR; ++r) g[r] = gb[kFold ? iB + r * 17 : padx((thi << 8) | (r << 4) | tlo)];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (v != 4 + q) lin_zeta_down<NR>(g, q);
         // B-layout slots belong to one thread each: written back in place
 #pragma unroll
-        for (int r = 0; r < NR; ++r) gb[padx((thi << 8) | (r << 4) | tlo)] = g[r];
+        for (int r = 0; r < NR; ++r) gb[kFold ? iB + r * 17 : padx((thi << 8) | (r << 4) | tlo)] = g[r];
         __syncthreads();
         // ---- B -> C, tile bits 8..11, live patterns only; results stay in place
         if (liveC) {
 #pragma unroll
-            for (int r = 0; r < NR; ++r) g[r] = gb[padx((r << 8) | pc)];
+            for (int r = 0; r < NR; ++r) g[r] = gb[kFold ? iC + r * 272 : padx((r << 8) | pc)];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (v != 8 + q) lin_zeta_down<NR>(g, q);
 #pragma unroll
-            for (int r = 0; r < NR; ++r) gb[padx((r << 8) | pc)] = g[r];
+            for (int r = 0; r < NR; ++r) gb[kFold ? iC + r * 272 : padx((r << 8) | pc)] = g[r];
         }
         __syncthreads();
         // ---- outputs: entries with at most d ones, read back through LDS.
