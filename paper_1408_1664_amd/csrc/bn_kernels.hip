@@ -1657,17 +1657,17 @@ __device__ inline void lin_zeta_down(double *g, int q) {
 //      register bit, the block of thread t + 2^(v-4) for tile bits 4..11,
 //      the tile H + v above the tile; one endpoint ahead of their use.
 //   B  x = thi * 256 + r * 16 + tlo, bits 4..7 in registers;
-//   C  x = r * 256 + p, p the thread's pattern of bits 0..7 (popcount order),
-//      bits 8..11 in registers. Only outputs with at most d ones are needed
-//      and bits 0..7 are final by then, so threads whose pattern has more
-//      than d ones skip C (whole waves for small d).
-// Two waves per SIMD: registers are capped to match (a few spill).
+//   C  x = r * 256 + p, p the thread's pattern of bits 0..7 (lane order
+//      ordC), bits 8..11 in registers. Only outputs with at most d ones are
+//      needed and bits 0..7 are final by then, so threads whose pattern has
+//      more than d ones skip C (whole waves for small d).
+// The kernels below wrap this body with their register caps.
 template <class P>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P::Store L,
-                 typename P::Store R, const typename P::V *__restrict__ qt,
-                 typename P::V *__restrict__ Y1, typename P::V *__restrict__ part,
-                 uint32_t *fb, uint32_t *rt) {
+__device__ __forceinline__ void
+gamma_tile_lin_body(int n, int d, int force_fb, GammaGeom gg, Tables tb,
+                    typename P::Store L, typename P::Store R, const typename P::V *__restrict__ qt,
+                    typename P::V *__restrict__ Y1, typename P::V *__restrict__ part,
+                    uint32_t *fb, uint32_t *rt) {
     using V = typename P::V;
     using R16 = typename P::Raw16;
     using A = typename P::Anchor;
@@ -1768,10 +1768,8 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
     // padx indices as a lane base plus a constant per register (folded into
     // the LDS offsets): A, padx(t * 16 + r) = 17 t + r; B, padx(thi * 256 +
     // r * 16 + tlo) = 272 thi + tlo + 17 r; C, padx(r * 256 + pc) =
-    // pc + pc / 16 + 272 r. The log form takes these (no spills then); the
-    // FP32-scaled form measured faster with the plain padx indices.
+    // pc + pc / 16 + 272 r
     const uint32_t iA = 17 * t, iB = 272 * thi + tlo, iC = pc + (pc >> 4);
-    constexpr bool kFold = !std::is_same<P, PolX32>::value;
     for (int v = 0; v < n; ++v) {
         const bool low = v < bT;
         if (!low && ((Hf >> v) & 1)) continue;
@@ -1814,26 +1812,26 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
             if (v != q) lin_zeta_down<NR>(g, q);
         // ---- A -> B, tile bits 4..7
 #pragma unroll
-        for (int r = 0; r < NR; ++r) gb[kFold ? iA + r : padx((t << 4) | r)] = g[r];
+        for (int r = 0; r < NR; ++r) gb[iA + r] = g[r];
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < NR; ++r) g[r] = gb[kFold ? iB + r * 17 : padx((thi << 8) | (r << 4) | tlo)];
+        for (int r = 0; r < NR; ++r) g[r] = gb[iB + r * 17];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (v != 4 + q) lin_zeta_down<NR>(g, q);
         // B-layout slots belong to one thread each: written back in place
 #pragma unroll
-        for (int r = 0; r < NR; ++r) gb[kFold ? iB + r * 17 : padx((thi << 8) | (r << 4) | tlo)] = g[r];
+        for (int r = 0; r < NR; ++r) gb[iB + r * 17] = g[r];
         __syncthreads();
         // ---- B -> C, tile bits 8..11, live patterns only; results stay in place
         if (liveC) {
 #pragma unroll
-            for (int r = 0; r < NR; ++r) g[r] = gb[kFold ? iC + r * 272 : padx((r << 8) | pc)];
+            for (int r = 0; r < NR; ++r) g[r] = gb[iC + r * 272];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (v != 8 + q) lin_zeta_down<NR>(g, q);
 #pragma unroll
-            for (int r = 0; r < NR; ++r) gb[kFold ? iC + r * 272 : padx((r << 8) | pc)] = g[r];
+            for (int r = 0; r < NR; ++r) gb[iC + r * 272] = g[r];
         }
         __syncthreads();
         // ---- outputs: entries with at most d ones, read back through LDS.
@@ -1866,6 +1864,27 @@ k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P
         __syncthreads();
     }
     if (t == 0 && sfail) fb_push(fb, H << 6);             // every endpoint
+}
+
+// Log form: two waves per SIMD, registers capped to match (no spills).
+template <class P>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P::Store L,
+                 typename P::Store R, const typename P::V *__restrict__ qt,
+                 typename P::V *__restrict__ Y1, typename P::V *__restrict__ part,
+                 uint32_t *fb, uint32_t *rt) {
+    gamma_tile_lin_body<P>(n, d, force_fb, gg, tb, L, R, qt, Y1, part, fb, rt);
+}
+
+// FP32-scaled form: three waves per SIMD (168 registers, some spill), which
+// measured faster than two without spills: more waves hide the barrier and
+// load latency of the endpoint loop.
+template <>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
+k_gamma_tile_lin<PolX32>(int n, int d, int force_fb, GammaGeom gg, Tables tb, PolX32::Store L,
+                         PolX32::Store R, const X32 *__restrict__ qt, X32 *__restrict__ Y1,
+                         X32 *__restrict__ part, uint32_t *fb, uint32_t *rt) {
+    gamma_tile_lin_body<PolX32>(n, d, force_fb, gg, tb, L, R, qt, Y1, part, fb, rt);
 }
 
 // Second chance for the endpoints that k_gamma_tile_lin could not scale from
