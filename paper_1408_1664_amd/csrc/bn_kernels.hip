@@ -1770,9 +1770,9 @@ gamma_tile_lin_body(int n, int d, int force_fb, GammaGeom gg, Tables tb,
     // r * 16 + tlo) = 272 thi + tlo + 17 r; C, padx(r * 256 + pc) =
     // pc + pc / 16 + 272 r
     const uint32_t iA = 17 * t, iB = 272 * thi + tlo, iC = pc + (pc >> 4);
-    for (int v = 0; v < n; ++v) {
+    auto endpoint = [&](const int v) {
         const bool low = v < bT;
-        if (!low && ((Hf >> v) & 1)) continue;
+        if (!low && ((Hf >> v) & 1)) return;
         const A T = sT[v];
         const int okv = sok[v];
         // ---- products in layout A (entries with bit v are not in the lattice)
@@ -1862,7 +1862,11 @@ gamma_tile_lin_body(int n, int d, int force_fb, GammaGeom gg, Tables tb,
             }
         }
         __syncthreads();
-    }
+    };
+    // the own Rp block is a partner only for the register bits 0..3: with a
+    // loop of their own, it is dead in the loop over the other endpoints
+    for (int v = 0; v < 4 && v < n; ++v) endpoint(v);
+    for (int v = 4; v < n; ++v) endpoint(v);
     if (t == 0 && sfail) fb_push(fb, H << 6);             // every endpoint
 }
 
