@@ -1661,7 +1661,7 @@ __device__ inline void lin_zeta_down(double *g, int q) {
 //      ordC), bits 8..11 in registers. Only outputs with at most d ones are
 //      needed and bits 0..7 are final by then, so threads whose pattern has
 //      more than d ones skip C (whole waves for small d).
-// The kernels below wrap this body with their register caps.
+// The kernel below wraps this body with its register cap.
 template <class P>
 __device__ __forceinline__ void
 gamma_tile_lin_body(int n, int d, int force_fb, GammaGeom gg, Tables tb,
@@ -1864,31 +1864,24 @@ gamma_tile_lin_body(int n, int d, int force_fb, GammaGeom gg, Tables tb,
         __syncthreads();
     };
     // the own Rp block is a partner only for the register bits 0..3: with a
-    // loop of their own, it is dead in the loop over the other endpoints
+    // loop of their own, it is dead in the loops over the other endpoints;
+    // the tile bits and the bits above the tile get a loop each as well
     for (int v = 0; v < 4 && v < n; ++v) endpoint(v);
-    for (int v = 4; v < n; ++v) endpoint(v);
+    for (int v = 4; v < bT && v < n; ++v) endpoint(v);
+    for (int v = bT; v < n; ++v) endpoint(v);
     if (t == 0 && sfail) fb_push(fb, H << 6);             // every endpoint
 }
 
-// Log form: two waves per SIMD, registers capped to match (no spills).
+// Three waves per SIMD (168 registers, some spill), which measured faster
+// than two without spills: more waves hide the barrier and load latency of
+// the endpoint loops.
 template <class P>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P::Store L,
                  typename P::Store R, const typename P::V *__restrict__ qt,
                  typename P::V *__restrict__ Y1, typename P::V *__restrict__ part,
                  uint32_t *fb, uint32_t *rt) {
     gamma_tile_lin_body<P>(n, d, force_fb, gg, tb, L, R, qt, Y1, part, fb, rt);
-}
-
-// FP32-scaled form: three waves per SIMD (168 registers, some spill), which
-// measured faster than two without spills: more waves hide the barrier and
-// load latency of the endpoint loop.
-template <>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
-k_gamma_tile_lin<PolX32>(int n, int d, int force_fb, GammaGeom gg, Tables tb, PolX32::Store L,
-                         PolX32::Store R, const X32 *__restrict__ qt, X32 *__restrict__ Y1,
-                         X32 *__restrict__ part, uint32_t *fb, uint32_t *rt) {
-    gamma_tile_lin_body<PolX32>(n, d, force_fb, gg, tb, L, R, qt, Y1, part, fb, rt);
 }
 
 // Second chance for the endpoints that k_gamma_tile_lin could not scale from
