@@ -109,6 +109,11 @@ SMALL = [
     (2, 50, 2, 1, 1, 1), (3, 0, 2, 2, 2, 2), (4, 17, 3, 2, 1, 3), (5, 100, 2, 3, 0, 4),
     (6, 250, [2, 3, 4, 2, 3, 2], 2, 2, 5), (7, 400, 2, 3, 6, 6), (9, 1000, 2, 3, 3, 7),
     (11, 300, 3, 2, 2, 8), (13, 500, 2, 4, 4, 9), (14, 64, 2, 2, 3, 10),
+    # large in-degree bounds on the 12-bit Gamma tile and the 13-bit alpha tile:
+    # most lanes of the pattern layouts are live (every lane group for d >= 5)
+    (15, 400, 2, 4, 6, 11), (16, 300, 2, 3, 8, 12),
+    # alpha seeds by blocks of tiles (n >= 22) with a large in-degree bound
+    (22, 200, 2, 3, 6, 13),
 ]
 
 
