@@ -2827,8 +2827,10 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
             rec(8);
             // 2^tl tiles per workgroup share its set-up (tables in LDS, the
             // colex terms of the thread's pattern)
+            // (tl < hA keeps the shift count nonnegative: at n = 14 there
+            // is a single tile per node and tl stays 0)
             int tl = 0;
-            while (tl < 6 && ((uint64_t)n << (hA - tl - 1)) >= 4096) ++tl;
+            while (tl < 6 && tl < hA && ((uint64_t)n << (hA - tl - 1)) >= 4096) ++tl;
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_lin<P>), dim3(nblkA >> tl), dim3(kThreads), smL,
                                st, n, d, a.KS, a.lin_mode == 2 ? 1 : 0, tl, (const double *)a.Zs,
                                (const double *)a.betal, a.K,
