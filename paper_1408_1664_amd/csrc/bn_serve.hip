@@ -9,6 +9,13 @@
 // device. Completion is observed through an event per request; the worker
 // then releases the request's device memory and admits more.
 //
+// The budget is charged with the device bytes a request really holds (its
+// block from the cache may be larger than the plan). When an admitted
+// request cannot get device memory while other solves are running, it goes
+// back to the head of the queue and admission pauses until one of them
+// completes; only a request that fails with nothing else on the device
+// resolves to BN_ENOMEM.
+//
 // The device work sits behind an Executor interface. BN_SERVE_FAKE=1 at
 // server creation selects a CPU executor (timed placeholder results) so the
 // scheduling logic -- admission, ordering, cancellation, failure paths --
@@ -50,7 +57,8 @@ struct Req {
     std::vector<uint8_t> data, arity;
     std::vector<double> log_rho, log_q;
     bn_precision prec = BN_FP32_SCALED;
-    size_t footprint = 0;
+    size_t footprint = 0;   // admission estimate (the plan, rounded as allocated)
+    size_t charged = 0;     // bytes counted against the budget while admitted
     // results
     std::vector<double> post;
     bn_report rep{};
@@ -69,6 +77,9 @@ class Executor {
     virtual size_t footprint(const Req &r) = 0;
     // Starts the solve; returns false (with r.status set) on failure.
     virtual bool start(Req &r) = 0;
+    // Device bytes the started request actually holds (a cached block may
+    // be larger than its footprint).
+    virtual size_t held(const Req &r) { return r.footprint; }
     // True once the solve has finished (results then written into r).
     virtual bool done(Req &r) = 0;
     virtual void release(Req &r) = 0;
@@ -104,8 +115,9 @@ class GpuExecutor : public Executor {
     }
     bool ok() const { return !streams_.empty(); }
     size_t footprint(const Req &r) override {
-        return make_plan(r.p.n, r.p.d, r.p.m, r.prec, true, true).total;
+        return round_up(make_plan(r.p.n, r.p.d, r.p.m, r.prec, true, true).total, kGranule);
     }
+    size_t held(const Req &r) override { return r.ws_bytes; }
     bool start(Req &r) override {
         (void)hipSetDevice(dev_);
         const Plan P = make_plan(r.p.n, r.p.d, r.p.m, r.prec, true, true);
@@ -182,6 +194,7 @@ class GpuExecutor : public Executor {
     }
 
    private:
+    static constexpr size_t kGranule = (size_t)2 << 20;   // device blocks: multiples of 2 MiB
     static size_t round_up(size_t x, size_t g) { return (x + g - 1) / g * g; }
     static bool take(std::multimap<size_t, void *> &c, size_t need, void **p, size_t *got) {
         auto it = c.lower_bound(need);
@@ -192,7 +205,7 @@ class GpuExecutor : public Executor {
         return true;
     }
     bool get_device(size_t bytes, void **p, size_t *got) {
-        const size_t need = round_up(bytes, (size_t)2 << 20);
+        const size_t need = round_up(bytes, kGranule);
         if (take(dev_cache_, need, p, got)) {
             dev_cached_ -= *got;
             return true;
@@ -385,8 +398,10 @@ class Server {
     void loop() {
         std::unique_lock<std::mutex> lk(mu_);
         while (true) {
-            // admit in arrival order while the head fits
-            while (!stop_ && !pending_.empty() && (int)running_.size() < max_active_ &&
+            // admit in arrival order while the head fits (and no admitted
+            // request is waiting for device memory to come back)
+            while (!stop_ && !mem_wait_ && !pending_.empty() &&
+                   (int)running_.size() < max_active_ &&
                    used_ + pending_.front()->footprint <= budget_) {
                 Req *r = pending_.front();
                 pending_.pop_front();
@@ -396,10 +411,21 @@ class Server {
                 lk.unlock();
                 const bool ok = ex_->start(*r);
                 lk.lock();
+                used_ -= r->footprint;
                 if (ok) {
+                    // charge what the request really holds
+                    r->charged = ex_->held(*r);
+                    used_ += r->charged;
                     running_.push_back(r);
+                } else if (r->status == BN_ENOMEM && !running_.empty()) {
+                    // the device is short while other solves hold memory:
+                    // the request goes back to the head of the queue and
+                    // admission waits for the next completion
+                    r->state = Req::PENDING;
+                    r->status = BN_EAGAIN;
+                    pending_.push_front(r);
+                    mem_wait_ = true;
                 } else {
-                    used_ -= r->footprint;
                     finish(r);
                     cv_done_.notify_all();
                 }
@@ -413,7 +439,8 @@ class Server {
                 if (fin) ex_->release(*r);
                 lk.lock();
                 if (fin) {
-                    used_ -= r->footprint;
+                    used_ -= r->charged;
+                    mem_wait_ = false;
                     finish(r);
                     running_.erase(running_.begin() + k);
                     any = true;
@@ -442,6 +469,7 @@ class Server {
     int max_active_;
     uint64_t next_ticket_ = 1;
     bool stop_ = false;
+    bool mem_wait_ = false;   // an admitted request found the device short of memory
     int pollers_ = 0;
     std::unique_ptr<Executor> ex_;
     std::thread worker_;

@@ -133,6 +133,19 @@ def test_injected_allocation_failure(fake):
     srv.close()
 
 
+def test_allocation_failure_while_others_run_is_retried(fake):
+    # the second request's allocation fails while the first holds the device:
+    # it goes back to the head of the queue and runs once the first completes
+    fake.setenv("BN_SERVE_FAIL_ALLOC", "2")
+    srv = bn.Server(max_active=2)
+    ts = [srv.submit(ds.data, ds.arity, 3) for ds in (_problem(9, seed=s) for s in range(3))]
+    out = [srv.poll(t, timeout_us=-1) for t in ts]
+    assert [o[0] for o in out] == [bn.BN_OK, bn.BN_OK, bn.BN_OK]
+    # it waited for the first request to finish (30 ms each)
+    assert out[1][2]["ms_queue"] > 20.0
+    srv.close()
+
+
 # ------------------------------------------------------------------ GPU
 
 def _mix(k=16):
