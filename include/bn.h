@@ -34,9 +34,15 @@
 
 #ifdef __cplusplus
 extern "C" {
+/* In C++ the enumerations get a fixed 32-bit underlying type, so that every
+ * int32 a C caller passes is a value of the type (the library rejects the
+ * unknown ones with BN_EINVAL); in C an enumeration is an int already. */
+#define BN_ENUM_BASE : int32_t
+#else
+#define BN_ENUM_BASE
 #endif
 
-typedef enum {
+typedef enum BN_ENUM_BASE {
     BN_OK = 0,
     BN_EINVAL = -1,     /* invalid argument (see each call)                        */
     BN_ENOMEM = -2,     /* the problem's footprint exceeds device memory or budget */
@@ -46,15 +52,20 @@ typedef enum {
     BN_EINTERNAL = -6   /* internal error                                          */
 } bn_status;
 
-typedef enum {
+typedef enum BN_ENUM_BASE {
     BN_FP64_LOG = 0,    /* every lattice value as an FP64 natural logarithm         */
-    BN_FP32_SCALED = 1  /* FP32 significand + 8-bit exponent (units of 2^64) per
-                           entry, on top of exact per-node (B_i) and per-layer (q)
-                           power-of-two scales; FP64 only in the log-gamma score
-                           sums, the scale exponents and the final 1/F(V) step     */
+    BN_FP32_SCALED = 1  /* values stored as an FP32 significand + 8-bit exponent
+                           (units of 2^64) per entry, on top of exact per-node (B_i)
+                           and per-layer (q) power-of-two scales; products and the
+                           sweep sums in FP32 significands with integer exponents.
+                           FP64 in the log-gamma score sums, the scale exponents,
+                           the final 1/F(V) step and the zeta adds inside a tile
+                           (plain doubles under one power-of-two scale per tile,
+                           or the FP32 form itself where the tile's range does
+                           not fit one FP64 scale)                                */
 } bn_precision;
 
-typedef enum {
+typedef enum BN_ENUM_BASE {
     BN_SCORE_BDEU = 0,  /* Dirichlet hyperparameters ess / (q r_i)               */
     BN_SCORE_K2 = 1     /* all Dirichlet hyperparameters 1                       */
 } bn_score;
@@ -118,14 +129,19 @@ size_t bn_num_parent_sets(int32_t n, int32_t d);
 bn_status bn_local_scores(const bn_problem *p, double *log_score);
 
 /* Device workspace needed by bn_edge_posteriors_dev for a given problem
- * shape (m: number of samples). */
+ * shape. The sample count m enters because the workspace also holds the
+ * score step's per-sample tables (bit planes of binary data and log-gamma
+ * values up to m). BN_EINVAL for n outside 2..31, d < 0, m < 0, an unknown
+ * precision or a NULL bytes. */
 bn_status bn_workspace_bytes(int32_t n, int32_t d, int32_t m, bn_precision prec,
                              size_t *bytes);
 
 /*
- * All n(n-1) edge posteriors from host data. Allocates its own device
- * workspace, copies the data, runs every step on the current HIP device
- * and blocks until done.
+ * All n(n-1) edge posteriors from host data: the whole of Algorithm 1 (local
+ * scores by Eq. 6, alpha by Eq. 7, the forward and backward sums of Eqs. 9
+ * and 10, Gamma by Eq. 12, and P(u -> v | D) by Eq. 11, divided by F(V) =
+ * P(D)). Allocates its own device workspace, copies the data, runs every
+ * step on the current HIP device and blocks until done.
  *   post: host, n*n doubles, post[u*n + v] = P(u -> v | D); diagonal 0.
  *   rep:  nullable; per-phase times are measured with HIP events.
  * BN_EINVAL as for bn_local_scores (and a bad precision); BN_ENOMEM when
@@ -152,9 +168,13 @@ bn_status bn_parent_set_posteriors(const bn_problem *p, bn_precision prec, doubl
 struct bn_timer;
 
 /*
- * Same computation with caller-supplied device memory and stream; nothing
- * is allocated. p->data must point to DEVICE memory (n*m bytes); arity,
- * log_rho and log_q are host arrays (copied into the workspace).
+ * The computation of bn_edge_posteriors (Algorithm 1; Eqs. 6, 7, 9-12) with
+ * caller-supplied device memory and stream, in stream order: nothing is
+ * allocated and nothing waits. p->data must point to DEVICE memory (n*m
+ * bytes); arity, log_rho and log_q are host arrays (consumed before the
+ * call returns). Results go to device buffers, and per-phase times to an
+ * optional bn_timer rather than a bn_report, which would need a wait;
+ * the caller synchronises the stream before reading any of them.
  *   dev_ws/ws_bytes: device workspace of at least bn_workspace_bytes().
  *   hip_stream:      a hipStream_t (NULL: the default stream).
  *   dev_post:        DEVICE, n*n doubles, written as for bn_edge_posteriors.
@@ -258,7 +278,7 @@ bn_status bn_modular_feature_posterior(const bn_problem *p, bn_precision prec,
  * kind, or a truncated (0 <= d < nbits) Moebius transform. Summation is in
  * FP64 in a fixed order (deterministic).
  */
-typedef enum {
+typedef enum BN_ENUM_BASE {
     BN_ZETA_UP = 0,
     BN_ZETA_DOWN = 1,
     BN_MOBIUS_UP = 2,

@@ -18,6 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bn_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
 _lib = None
 
 BDEU = 0
@@ -34,12 +35,28 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_sanitized() -> str:
+    """The oracle under gcc's AddressSanitizer and UndefinedBehaviorSanitizer
+    (liboracle_san.so; loaded with libasan preloaded and ORACLE_LIBRARY
+    pointing at it)."""
+    tmp = _LIB_SAN + ".tmp"
+    subprocess.run(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=all", "-std=c11", "-fopenmp", "-shared", "-fPIC",
+                    "-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, _LIB_SAN)
+    return _LIB_SAN
+
+
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        # ORACLE_LIBRARY selects another build of the oracle (build_sanitized())
+        path = os.environ.get("ORACLE_LIBRARY")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         lib.or_local_scores.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_double, P, ctypes.c_int]

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbnpost.so")
+# BN_LIBRARY selects another build of the same library (the sanitizer build
+# of the host code, libbnpost_san.so, for the CPU tests under ASan/UBSan).
+LIB_PATH = os.environ.get("BN_LIBRARY") or os.path.join(_HERE, "libbnpost.so")
 
 BN_OK, BN_EINVAL, BN_ENOMEM, BN_EDEVICE, BN_EAGAIN, BN_ECANCELED, BN_EINTERNAL = (
     0, -1, -2, -3, -4, -5, -6)
@@ -133,8 +135,10 @@ class _ProblemHold:
     """A bn_problem plus the host arrays it points to (kept alive)."""
 
     def __init__(self, data, arity, d, score="bdeu", ess=1.0, log_rho=None, log_q=None,
-                 data_ptr=None):
-        if data_ptr is None:
+                 data_ptr=None, device=False):
+        """data: host array [n, m]; or, with device=True, the shape (n, m) of
+        device data at data_ptr (None when m = 0)."""
+        if not device and data_ptr is None:
             self.data = np.ascontiguousarray(data, dtype=np.uint8)
             n, m = self.data.shape
             dp = self.data.ctypes.data if m > 0 else None
@@ -245,7 +249,7 @@ def edge_posteriors_dev(data_dev, arity, d, precision, ws, post_dev, diag_dev=No
     assert data_dev.dtype == torch.uint8 and data_dev.is_contiguous() and data_dev.is_cuda
     assert post_dev.dtype == torch.float64 and post_dev.numel() >= n * n and post_dev.is_cuda
     h = _ProblemHold((n, m), arity, d, score, ess, log_rho, log_q,
-                     data_ptr=data_dev.data_ptr() if m > 0 else None)
+                     data_ptr=data_dev.data_ptr() if m > 0 else None, device=True)
     st = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
     _check(lib().bn_edge_posteriors_dev(h.ref(), _PREC[precision], ctypes.c_void_p(ws.data_ptr()),
                                         ws.numel() * ws.element_size(), ctypes.c_void_p(st),

@@ -16,14 +16,26 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Wno-unused-command-line-argument"]
 
 
-def build(verbose: bool = False) -> str:
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer (device code is
+# built as usual): each option applies to the host compilation only.
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+LIB_SAN = os.path.join(HERE, "libbnpost_san.so")
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile every source for gfx950 and link libbnpost.so; with sanitize,
+    libbnpost_san.so with the host code under ASan and UBSan (loaded with
+    the sanitizer runtime preloaded, BN_LIBRARY pointing at it)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    flags = FLAGS + (SAN_FLAGS if sanitize else [])
+    out_lib = LIB_SAN if sanitize else LIB
     with tempfile.TemporaryDirectory() as td:
         objs = []
         procs = []
         for s in SOURCES:
             obj = os.path.join(td, s + ".o")
-            cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, s), "-o", obj]
+            cmd = [hipcc, *flags, "-c", os.path.join(CSRC, s), "-o", obj]
             procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE,
                                               stderr=subprocess.STDOUT, text=True)))
             objs.append(obj)
@@ -34,12 +46,15 @@ def build(verbose: bool = False) -> str:
                 raise RuntimeError(f"hipcc failed on {s}")
             if verbose and out.strip():
                 sys.stderr.write(out)
-        tmp = LIB + ".tmp"
-        subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
-                        "-lpthread"], check=True)
-        os.replace(tmp, LIB)
-    return LIB
+        tmp = out_lib + ".tmp"
+        link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
+        if sanitize:
+            link += ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                     "-Xarch_host", "-shared-libsan"]
+        subprocess.run(link, check=True)
+        os.replace(tmp, out_lib)
+    return out_lib
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, sanitize="--sanitize" in sys.argv))
