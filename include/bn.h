@@ -193,6 +193,33 @@ bn_status bn_edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *d
                                  double *dev_diag, struct bn_timer *timer);
 
 /*
+ * Allocation-free variant of bn_edge_posteriors_dev, for callers that cannot
+ * allocate device memory during a solve: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc. The workspace is a static
+ * device array of BN_NOALLOC_MAX_BYTES inside the library (one per GPU,
+ * held from the library's loading until the process ends); the call itself
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ *   p, prec:    as for bn_edge_posteriors_dev (p->data in DEVICE memory).
+ *   hip_stream: a hipStream_t (NULL: the default stream).
+ *   dev_post:   DEVICE, n*n doubles, as for bn_edge_posteriors_dev.
+ *   dev_diag:   DEVICE or NULL, 8 doubles, as for bn_edge_posteriors_dev.
+ * Enqueues the work and returns without waiting; the results are valid after
+ * the stream is synchronised, and bit-identical to bn_edge_posteriors_dev on
+ * the same inputs. Every call on one GPU shares that GPU's array: calls whose
+ * work overlaps on the device (other streams, or other threads, before the
+ * previous call's stream has finished) race and give undefined results.
+ * Each solve initialises everything it reads, so the previous call's
+ * contents need no clearing.
+ * BN_EINVAL as for bn_edge_posteriors_dev; BN_ENOMEM when the problem's
+ * workspace (bn_workspace_bytes) exceeds BN_NOALLOC_MAX_BYTES (256 MiB;
+ * with d = 3 and m <= 2000 that admits n <= 21 in either form);
+ * BN_EDEVICE when the array's device address cannot be obtained.
+ */
+#define BN_NOALLOC_MAX_BYTES ((size_t)256 << 20)
+bn_status bn_edge_posteriors_noalloc(const bn_problem *p, bn_precision prec, void *hip_stream,
+                                     double *dev_post, double *dev_diag);
+
+/*
  * Phase timer: HIP events that bn_edge_posteriors_dev records on the solve's
  * own stream between its phases when a non-NULL timer is passed (recording
  * does not synchronise). Create it on the device that runs the solves.

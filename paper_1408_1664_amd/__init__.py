@@ -33,7 +33,10 @@ EXPORTED = ["bn_num_parent_sets", "bn_local_scores", "bn_workspace_bytes",
             "bn_timer_create",
             "bn_timer_destroy", "bn_timer_read", "bn_server_create", "bn_serve_submit",
             "bn_serve_poll", "bn_server_destroy", "bn_subset_transform",
-            "bn_modular_feature_posterior", "bn_status_string"]
+            "bn_modular_feature_posterior", "bn_status_string", "bn_edge_posteriors_noalloc"]
+
+# Largest workspace the allocation-free entry point takes (BN_NOALLOC_MAX_BYTES).
+NOALLOC_MAX_BYTES = 256 << 20
 
 
 class BnError(RuntimeError):
@@ -93,6 +96,8 @@ def lib():
         L.bn_parent_set_posteriors.argtypes = [P, ctypes.c_int, P, P, P]
         L.bn_parent_set_posteriors.restype = ctypes.c_int
         L.bn_edge_posteriors_dev.argtypes = [P, ctypes.c_int, P, ctypes.c_size_t, P, P, P, P]
+        L.bn_edge_posteriors_noalloc.argtypes = [P, ctypes.c_int, P, P, P]
+        L.bn_edge_posteriors_noalloc.restype = ctypes.c_int
         L.bn_timer_create.argtypes = [P]
         L.bn_timer_create.restype = ctypes.c_int
         L.bn_timer_destroy.argtypes = [P]
@@ -258,6 +263,28 @@ def edge_posteriors_dev(data_dev, arity, d, precision, ws, post_dev, diag_dev=No
                                         else ctypes.c_void_p(diag_dev.data_ptr()),
                                         None if timer is None else timer._h),
            "bn_edge_posteriors_dev")
+
+
+def edge_posteriors_noalloc(data_dev, arity, d, precision, post_dev, diag_dev=None,
+                            stream=None, score="bdeu", ess=1.0, log_rho=None, log_q=None):
+    """Enqueue a solve that allocates nothing (bn_edge_posteriors_noalloc):
+    the library's static device array is the workspace, so it takes
+    problems whose workspace_bytes() is at most NOALLOC_MAX_BYTES. Arguments
+    as for edge_posteriors_dev without ws and timer. Calls whose work
+    overlaps on one GPU share that array and race."""
+    import torch
+
+    n, m = int(data_dev.shape[0]), int(data_dev.shape[1])
+    assert data_dev.dtype == torch.uint8 and data_dev.is_contiguous() and data_dev.is_cuda
+    assert post_dev.dtype == torch.float64 and post_dev.numel() >= n * n and post_dev.is_cuda
+    h = _ProblemHold((n, m), arity, d, score, ess, log_rho, log_q,
+                     data_ptr=data_dev.data_ptr() if m > 0 else None, device=True)
+    st = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+    _check(lib().bn_edge_posteriors_noalloc(h.ref(), _PREC[precision], ctypes.c_void_p(st),
+                                            ctypes.c_void_p(post_dev.data_ptr()),
+                                            None if diag_dev is None
+                                            else ctypes.c_void_p(diag_dev.data_ptr())),
+           "bn_edge_posteriors_noalloc")
 
 
 def modular_feature_posterior(data, arity, d, log_f, precision="fp64", score="bdeu", ess=1.0,

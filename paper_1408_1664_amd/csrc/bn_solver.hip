@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/bn.h"
@@ -529,6 +530,55 @@ bn_status feature_posterior_host(const bn_problem *p, bn_precision prec, const d
     return BN_OK;
 }
 
+// ------------------------------------------------ allocation-free variant
+// The workspace of bn_edge_posteriors_noalloc: a static device array. Each
+// GPU the library runs on holds its own copy, at its own address, from the
+// loading of the library until the process ends. In host code the array's
+// name is only a stand-in for the symbol; the device address comes from
+// hipGetSymbolAddress, once per device, and is the only form that reaches a
+// kernel.
+static __device__ __align__(256) unsigned char scratch[BN_NOALLOC_MAX_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (resolved on the
+// first call on that device, with that device current).
+static bn_status scratch_of_current_device(char **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BN_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return BN_EDEVICE;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = reinterpret_cast<char *>(g_scratch_ptr[dev]);
+    return BN_OK;
+}
+
+bn_status edge_posteriors_noalloc(const bn_problem *p, bn_precision prec, void *hip_stream,
+                                  double *dev_post, double *dev_diag) {
+    bn_status s = validate(p, false, false);
+    if (s != BN_OK) return s;
+    if (!dev_post) return BN_EINVAL;
+    if (prec != BN_FP64_LOG && prec != BN_FP32_SCALED) return BN_EINVAL;
+    Plan P = make_plan(p->n, p->d, p->m, prec, false, false);
+    if (P.total > (size_t)BN_NOALLOC_MAX_BYTES) return BN_ENOMEM;
+    char *ws = nullptr;
+    s = scratch_of_current_device(&ws);
+    if (s != BN_OK) return s;
+    // Every kernel of the solve initialises what it later reads (counters,
+    // lists and partial sums included), so the previous call's contents need
+    // no clearing.
+    return enqueue_solve(P, p, p->data, ws, reinterpret_cast<hipStream_t>(hip_stream), dev_post,
+                         dev_diag, nullptr);
+}
+
 bn_status edge_posteriors_dev(const bn_problem *p, bn_precision prec, void *dev_ws,
                               size_t ws_bytes, void *hip_stream, double *dev_post,
                               double *dev_diag, PhaseEvents *ev) {
@@ -579,6 +629,11 @@ bn_status bn_modular_feature_posterior(const bn_problem *p, bn_precision prec,
                                        const double *log_f, double *expectation,
                                        double *log_pair) {
     return bnk::feature_posterior_host(p, prec, log_f, expectation, log_pair);
+}
+
+bn_status bn_edge_posteriors_noalloc(const bn_problem *p, bn_precision prec, void *hip_stream,
+                                     double *dev_post, double *dev_diag) {
+    return bnk::edge_posteriors_noalloc(p, prec, hip_stream, dev_post, dev_diag);
 }
 
 struct bn_timer {

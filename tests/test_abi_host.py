@@ -148,3 +148,22 @@ def test_modular_feature_rejects_bad_arguments():
         assert L.bn_modular_feature_posterior(h.ref(), 1, bn._ptr(lf2), bn._ptr(out), None) == bn.BN_EINVAL
     with pytest.raises(ValueError):
         bn.modular_feature_posterior(data, arity, 2, np.zeros((4, K + 1)))
+
+
+def test_noalloc_rejects_problems_beyond_its_array():
+    # checked against bn_workspace_bytes before any device call: a problem
+    # whose workspace exceeds the static array gets BN_ENOMEM, and an
+    # invalid one BN_EINVAL, without touching the (fake) device pointers
+    import ctypes
+    L = bn.lib()
+    fake = ctypes.c_void_p(0x1000)
+    for n, prec in [(22, 0), (22, 1), (25, 1)]:
+        assert bn.workspace_bytes(n, 3, 100, prec) > bn.NOALLOC_MAX_BYTES
+        h = bn._ProblemHold((n, 100), np.full(n, 2, np.uint8), 3, data_ptr=0x1000)
+        assert L.bn_edge_posteriors_noalloc(h.ref(), prec, None, fake, None) == bn.BN_ENOMEM
+    for n, prec in [(21, 1), (21, 0)]:
+        assert bn.workspace_bytes(n, 3, 2000, prec) <= bn.NOALLOC_MAX_BYTES
+    h = bn._ProblemHold((12, 100), np.full(12, 2, np.uint8), 3, data_ptr=0x1000)
+    assert L.bn_edge_posteriors_noalloc(h.ref(), 1, None, None, None) == bn.BN_EINVAL
+    assert L.bn_edge_posteriors_noalloc(h.ref(), 7, None, fake, None) == bn.BN_EINVAL
+    assert L.bn_edge_posteriors_noalloc(None, 1, None, fake, None) == bn.BN_EINVAL
