@@ -47,7 +47,36 @@ def kernel_bytes(phase, n, prec):
     raise ValueError(phase)
 
 
-def measure(bn, torch, datagen, name, prec, steps, warmup):
+# Variants of a comparison line: environment settings read by the library's
+# plan (at each call), so the same entry point times another form.
+VARIANTS = {
+    "": {},
+    # alpha never materialised: the sweeps rebuild it from 9-bit block seeds
+    # (the library's choice only where alpha would not fit the device)
+    "fused": {"BN_FUSED_ALPHA": "1"},
+    # alpha materialised whatever the size (the default up to n = 31)
+    "mat": {"BN_FUSED_ALPHA": "0"},
+    # no linear tiles: every zeta step in the FP32-scaled form itself (FP32
+    # significand adds with exponent alignment), alpha materialised
+    "nolin": {"BN_LINEAR_TILES": "0"},
+}
+
+
+def measure(bn, torch, datagen, name, prec, steps, warmup, variant=""):
+    env = VARIANTS[variant]
+    saved = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return _measure(bn, torch, datagen, name, prec, steps, warmup, variant)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def _measure(bn, torch, datagen, name, prec, steps, warmup, variant):
     ds, p = datagen.workload(name)
     n, m, d = ds.n, ds.m, p["d"]
     ws = torch.empty(bn.workspace_bytes(n, d, m, prec), dtype=torch.uint8, device="cuda")
@@ -71,11 +100,15 @@ def measure(bn, torch, datagen, name, prec, steps, warmup):
     ph = [timers[warmup + k].read() for k in range(steps)]
     phases = {key: sum(x[key] for x in ph) / steps for key in ph[0]}
     dg = diag.cpu().tolist()
-    res = dict(workload=name, precision=prec, n=n, m=m, d=d, steps=steps, warmup=warmup,
+    res = dict(workload=name, precision=prec, variant=variant or "default", n=n, m=m, d=d,
+               steps=steps, warmup=warmup, workspace_bytes=ws.numel(),
                seconds=sec, ms_per_step=1e3 * sec / steps,
                cells_per_s=n * 2 ** n * steps / sec, phases_ms=phases, log_LV=dg[0],
                max_invariant_residual=dg[1], saturated=int(dg[2]), flushed=int(dg[3]),
-               post=post.cpu().numpy())
+               fallback=int(dg[7]), post=post.cpu().numpy())
+    # the library's plan holds alpha (5 bytes per entry) unless the fused
+    # sweeps run: a smaller workspace means alpha is never materialised
+    res["fused"] = prec == "fp32" and res["workspace_bytes"] < 5 * n * 2 ** (n - 1)
     for t in timers:
         t.close()
     del ws, data, post, diag
@@ -120,15 +153,45 @@ def counter_traffic(kernel, workload, prec):
 
 def roofline(res):
     """HBM roofline of the dominant single-launch kernel: algorithmic bytes of
-    its launch over its HIP-event duration (averaged over the timed steps)."""
+    its launch over its HIP-event duration (averaged over the timed steps).
+    The alpha tile kernel exists only when alpha is materialised; with the
+    fused sweeps its timer entry brackets the block seeds instead, so the
+    candidate there is the Gamma tile alone."""
     n, prec, ph = res["n"], res["precision"], res["phases_ms"]
-    dom = max(SINGLE_LAUNCH, key=lambda k: ph[k])
+    cands = [k for k in SINGLE_LAUNCH if not (k == "alpha_tile" and res.get("fused"))]
+    dom = max(cands, key=lambda k: ph[k])
     b = kernel_bytes(dom, n, prec)
     ach = b / (ph[dom] * 1e-3) / 1e9
+    traffic = counter_traffic(SINGLE_LAUNCH[dom], res["workload"], prec)
     return dict(kernel=SINGLE_LAUNCH[dom], ms=ph[dom], bound="hbm", achieved=ach,
-                peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                traffic=counter_traffic(SINGLE_LAUNCH[dom], res["workload"], prec),
-                algorithmic_bytes=b)
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=traffic,
+                algorithmic_bytes=b,
+                achieved_counted=None if traffic is None else traffic / (ph[dom] * 1e-3) / 1e9)
+
+
+def solve_bytes(res):
+    """Algorithmic HBM bytes of one whole solve, E bytes per stored value:
+    with alpha materialised, E (2.5 n 2^n + 4 2^n) (alpha written once and
+    read by both sweeps, the L and Rp halves read for every Gamma endpoint,
+    L and Rp written and read); with the fused sweeps the alpha terms are
+    gone and the block seeds are written once and read by both sweeps."""
+    n, d, E = res["n"], res["d"], STORE_BYTES[res["precision"]]
+    mat = E * (2.5 * n * 2 ** n + 4 * 2 ** n)
+    if not res.get("fused"):
+        return mat, mat
+    ks9 = sum(math.comb(9, k) for k in range(d))
+    seeds = 3 * E * n * 2 ** (n - 10) * ks9
+    return mat, E * (n * 2 ** n + 4 * 2 ** n) + seeds
+
+
+def solve_roofline(res):
+    mat, method = solve_bytes(res)
+    sec = res["ms_per_step"] * 1e-3
+    return dict(ms=res["ms_per_step"], bytes_method=method, GBs_method=method / sec / 1e9,
+                frac_method=method / sec / 1e9 / HBM_PEAK_GBS,
+                bytes_materialised_accounting=mat,
+                GBs_materialised_accounting=mat / sec / 1e9,
+                frac_materialised_accounting=mat / sec / 1e9 / HBM_PEAK_GBS)
 
 
 def copy_calibration(nbytes):
@@ -143,7 +206,7 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
 
 
-def serving(bn, datagen, num=512, check=8):
+def serving(bn, datagen, num=512, check=512):
     """Serving stream: 512 requests, n ~ U{10..22}, m ~ U{100..2000}, arity
     in {2,3}, d = 3, FP32-scaled. Closed-loop saturation first (all requests
     at t = 0), then open-loop Poisson arrivals at 0.5 and 0.8 of that rate;
@@ -188,15 +251,22 @@ def serving(bn, datagen, num=512, check=8):
                     p99_ms=float(np.percentile(lat, 99))), posts
 
     sat, posts = run(None)
-    same = True
+    # every request of the closed-loop mix against the same problem solved
+    # alone (bitwise: the kernels reduce in a fixed order)
+    same, ndiff, maxdiff = True, 0, 0.0
     for j in range(check):
         alone, _ = bn.edge_posteriors(data[j].data, data[j].arity, reqs[j]["d"], precision="fp32",
                                       ess=reqs[j]["ess"])
-        same = same and bool(np.array_equal(alone, posts[j]))
+        eq = bool(np.array_equal(alone, posts[j]))
+        same = same and eq
+        if not eq:
+            ndiff += 1
+            maxdiff = max(maxdiff, float(np.abs(alone - posts[j]).max()))
     rng = np.random.default_rng(4)
     out = dict(requests=num, workload="512 requests, n~U{10..22}, m~U{100..2000}, arity~U{2,3}, "
                                        "d=3, FP32-scaled",
-               closed_loop=sat, open_loop=[], served_equals_alone=same, checked=check)
+               closed_loop=sat, open_loop=[], served_equals_alone=same, checked=check,
+               differing=ndiff, max_abs_diff=maxdiff)
     for frac in (0.5, 0.8):
         rate = frac * sat["solves_per_s"]
         gaps = rng.exponential(1.0 / rate, size=num)
@@ -256,9 +326,13 @@ def main():
     ap.add_argument("--workload", default="n30_binary_m500_d3")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--compare", default="fp64@n30_binary_m500_d3:3,"
+                                         "fp32+fused@n30_binary_m500_d3:3,"
+                                         "fp32+nolin@n30_binary_m500_d3:2,"
                                          "fp32@n25_binary_m2000_d4:10,"
                                          "fp64@n25_binary_m2000_d4:5",
-                    help="extra lines prec@workload:steps, comma separated ('' for none)")
+                    help="extra lines prec[+variant]@workload:steps, comma separated ('' for "
+                         "none); variants: fused (alpha never materialised), mat (alpha materialised), "
+                         "nolin (no linear tiles)")
     ap.add_argument("--cpu-sample-n", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -299,16 +373,18 @@ def main():
     comps = []
     for item in [c for c in args.compare.split(",") if c.strip()]:
         pw, st = item.split(":")
-        prec, wl = pw.split("@")
-        r = measure(bn, torch, datagen, wl, prec, int(st), 1)
+        pv, wl = pw.split("@")
+        prec, _, variant = pv.partition("+")
+        r = measure(bn, torch, datagen, wl, prec, int(st), 1, variant)
         line = {k: v for k, v in r.items() if k != "post"}
-        if wl == args.workload and prec != args.precision:
+        if wl == args.workload:
             line["max_abs_posterior_diff_vs_headline"] = float(np.abs(r["post"] -
                                                                       head["post"]).max())
         line["roofline"] = roofline(r)
+        line["solve_roofline"] = solve_roofline(r)
         comps.append(line)
-        print(f"# {wl} {prec}: {r['ms_per_step']:.2f} ms/step, {r['cells_per_s']:.3e} cells/s",
-              file=sys.stderr, flush=True)
+        print(f"# {wl} {pv}: {r['ms_per_step']:.2f} ms/step, {r['cells_per_s']:.3e} cells/s, "
+              f"phases {r['phases_ms']}", file=sys.stderr, flush=True)
     serve = None
     if not args.no_serving:
         serve = serving(bn, datagen)
@@ -336,14 +412,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        # FP32-scaled: FP32 significands (with integer exponents) in storage,
+        # products and sweep sums; FP64 zeta adds inside a tile and FP64
+        # log-gamma scores
+        "dtype": "f32+f64" if args.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": head["n"], "m": head["m"], "d": head["d"],
                    "precision": "fp32_scaled" if args.precision == "fp32" else "fp64_log",
+                   "alpha": "never materialised (fused sweeps)" if head["fused"]
+                            else "materialised",
                    "score": "BDeu(ess=1)", "prior": "q=1, rho_k=1/C(n-1,k)"},
         "roofline": {k: rf[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_kernel": rf["kernel"],
         "roofline_kernel_ms": rf["ms"],
+        "roofline_achieved_counted": rf["achieved_counted"],
+        "solve_roofline": solve_roofline(head),
+        "workspace_bytes": head["workspace_bytes"],
+        "fallback": head["fallback"],
         "cpu_baseline": cpu,
         "phases_ms": head["phases_ms"],
         "log_LV": head["log_LV"],

@@ -9,7 +9,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbnpost.so")
-SOURCES = ["bn_kernels.hip", "bn_solver.hip", "bn_serve.hip", "bn_subset.hip"]
+SOURCES = ["bn_kernels.hip", "bn_fused.hip", "bn_solver.hip", "bn_serve.hip", "bn_subset.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

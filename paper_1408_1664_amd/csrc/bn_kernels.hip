@@ -149,6 +149,19 @@ __global__ void k_ranked(const uint32_t *binom, int w, int d, uint32_t *out) {
     out[r] = x;
 }
 
+// Masks over w bits by popcount, then colex order (the sweep tiles' high
+// parts, so that a workgroup reads its tile's mask instead of unranking it).
+__global__ void k_hiorder(const uint32_t *binom, int w, uint32_t *out) {
+    const uint32_t x = blockIdx.x * kThreads + threadIdx.x;
+    if (x >> w) return;
+    const int k = __popc(x);
+    uint32_t r = Kcount(binom, w, k - 1);
+    int j = 0;
+    for (int p = 0; p < w; ++p)
+        if ((x >> p) & 1) r += C(binom, p, ++j);
+    out[r] = x;
+}
+
 // Compressed parent-set masks in rank order, K(N,d) of them.
 __global__ void k_famask(const uint32_t *binom, int N, int d, uint32_t K, uint32_t *famask) {
     uint32_t r = blockIdx.x * kThreads + threadIdx.x;
@@ -535,10 +548,12 @@ __device__ inline void lin_zeta_up(double *v, int q) {
 // 2^1900: no partial sum can then leave the double range (K(n-1, d) <
 // 2^31). betal_i(r) = B_i(r) under that scale. Nodes that do not qualify
 // (linok = 0) are computed in the number system proper.
+// emax (nullable) receives floor(log2 max_G B_i(G)) + 1 per node (the bound
+// the fused sweeps test their blocks against).
 template <class P>
 __global__ void k_prep_lin(int n, uint32_t K, const typename P::V *__restrict__ beta,
                            double *__restrict__ betal, typename P::Anchor *__restrict__ anc,
-                           int *__restrict__ linok) {
+                           int *__restrict__ linok, int *__restrict__ emax) {
     using A = typename P::Anchor;
     __shared__ double red[kThreads];
     __shared__ int sok;
@@ -556,6 +571,7 @@ __global__ void k_prep_lin(int n, uint32_t K, const typename P::V *__restrict__ 
         sT = T;
         anc[i] = T;
         linok[i] = sok;
+        if (emax) emax[i] = mx > -1e300 ? (int)mx + 1 : -(1 << 26);
     }
     __syncthreads();
     if (!sok) return;
@@ -1280,8 +1296,8 @@ __device__ inline void cross_terms(const typename P::Store &alpha, const typenam
 // layer. Requires bL >= 2.
 template <class P>
 __global__ void __launch_bounds__(kThreads)
-k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Store L,
-      unsigned long long *cnt) {
+k_fwd(int n, int bL, int h, uint32_t hoff, Tables tb, typename P::Store alpha,
+      typename P::Store L, unsigned long long *cnt) {
     using V = typename P::V;
     extern __shared__ unsigned char smem[];
     const uint32_t half = 1u << (bL - 1);
@@ -1294,8 +1310,11 @@ k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
     const int t = threadIdx.x;
     const uint64_t NN = 1ull << (n - 1);
     if (t == 0) {
-        colex_unrank(tb.binom, blockIdx.x, h, pos);
-        for (int q = 0; q < h; ++q) pos[q] += bL;   // node indices of H
+        uint32_t Hm = tb.hord[hoff + blockIdx.x];   // H over the high bits
+        for (int q = 0; q < h; ++q) {
+            pos[q] = bL + __ffs(Hm) - 1;            // node indices of H
+            Hm &= Hm - 1;
+        }
     }
     if (t < bL + 2) loff[t] = tb.loff[t];
     for (uint32_t x = t; x < T; x += kThreads) lord[x] = tb.lorder[x];
@@ -1338,8 +1357,8 @@ k_fwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
 // the top. Same tiling as the forward sweep, mirrored. Requires bL >= 2.
 template <class P>
 __global__ void __launch_bounds__(kThreads)
-k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Store R,
-      unsigned long long *cnt) {
+k_bwd(int n, int bL, int h, uint32_t hoff, Tables tb, typename P::Store alpha,
+      typename P::Store R, unsigned long long *cnt) {
     using V = typename P::V;
     extern __shared__ unsigned char smem[];
     const uint32_t half = 1u << (bL - 1);
@@ -1355,9 +1374,12 @@ k_bwd(int n, int bL, int h, Tables tb, typename P::Store alpha, typename P::Stor
     const int nh = n - bL;
     const uint64_t NN = 1ull << (n - 1);
     if (t == 0) {
-        colex_unrank(tb.binom, blockIdx.x, h, pos);
-        uint32_t Hm = 0;
-        for (int q = 0; q < h; ++q) Hm |= 1u << pos[q];
+        const uint32_t Hm = tb.hord[hoff + blockIdx.x];   // H over the high bits
+        uint32_t rest = Hm;
+        for (int q = 0; q < h; ++q) {
+            pos[q] = __ffs(rest) - 1;
+            rest &= rest - 1;
+        }
         int no = 0;
         for (int p = 0; p < nh; ++p)
             if (!((Hm >> p) & 1)) outs[no++] = bL + p;   // nodes above the tile, not in H
@@ -2732,7 +2754,20 @@ hipError_t launch_setup(const Tables &tb, int bL, int W, int bG, int bA, int d, 
     hipLaunchKernelGGL(k_famask, dim3((K + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
                        (const uint32_t *)tb.binom, (int)N, d, K, tb.famask);
     BN_CHECK_LAUNCH();
+    const int nh = (int)N + 1 - bL;
+    hipLaunchKernelGGL(k_hiorder, dim3(((1u << nh) + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                       st, (const uint32_t *)tb.binom, nh, tb.hord);
+    BN_CHECK_LAUNCH();
     return hipSuccess;
+}
+
+uint32_t hord_offset(int nh, int h) {
+    uint64_t s = 0, c = 1;
+    for (int k = 0; k < h; ++k) {
+        s += c;
+        c = c * (uint64_t)(nh - k) / (uint64_t)(k + 1);
+    }
+    return (uint32_t)s;
 }
 
 hipError_t launch_scores(int n, int m, const uint8_t *data, const uint8_t *arity, uint32_t K,
@@ -2771,6 +2806,14 @@ static uint32_t host_kcount(int w, int t) {
 }
 
 template <class P>
+static hipError_t launch_gamma_edges(const LatticeArgs &a, const typename P::Store &L,
+                                     const typename P::Store &R, hipStream_t st,
+                                     PhaseEvents *ev);
+static hipError_t launch_lattice_fused(const LatticeArgs &a, const PolX32::Store &L,
+                                       const PolX32::Store &R, hipStream_t st,
+                                       PhaseEvents *ev);
+
+template <class P>
 hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
                           const typename P::Store &L, const typename P::Store &R,
                           hipStream_t st, PhaseEvents *ev) {
@@ -2793,6 +2836,9 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
                        a.gauge_exp, a.fbA, a.fbG, a.rtG);
     BN_CHECK_LAUNCH();
     rec(1);
+    if constexpr (std::is_same<P, PolX32>::value) {
+        if (a.fused) return launch_lattice_fused(a, L, R, st, ev);
+    }
     if (a.bA == 13) {
         const uint32_t nit = (uint32_t)a.nitA;
         // the partial-rank table is used when ranks fit 16 bits and it fits 12 KB
@@ -2803,7 +2849,7 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
         if (a.lin_mode && a.Zs) {
             using A = typename P::Anchor;
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prep_lin<P>), dim3(n), dim3(kThreads), 0, st, n,
-                               a.K, (const V *)beta, a.betal, (A *)a.anc, a.linok);
+                               a.K, (const V *)beta, a.betal, (A *)a.anc, a.linok, nullptr);
             BN_CHECK_LAUNCH();
             // block-wise seeds: 2^bS tiles per workgroup, 4 <= bS <= 8, with at
             // least 4 high bits left so that the grid holds n * 16 workgroups
@@ -2867,8 +2913,8 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
                        sizeof(V) * ((size_t)1 << a.bL) + 2 * ((size_t)1 << a.bL);
     for (int h = 0; h <= nh; ++h) {
         const unsigned nb = a.tiles_per_layer[h];
-        hipLaunchKernelGGL(k_fwd<P>, dim3(nb), dim3(kThreads), smL, st, n, a.bL, h, tb, alpha, L,
-                           a.cnt);
+        hipLaunchKernelGGL(k_fwd<P>, dim3(nb), dim3(kThreads), smL, st, n, a.bL, h,
+                           hord_offset(nh, h), tb, alpha, L, a.cnt);
         BN_CHECK_LAUNCH();
     }
     rec(3);
@@ -2882,11 +2928,33 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     }
     for (int h = nh; h >= 0; --h) {
         const unsigned nb = a.tiles_per_layer[h];
-        hipLaunchKernelGGL(k_bwd<P>, dim3(nb), dim3(kThreads), smL, st, n, a.bL, h, tb, alpha, R,
-                           a.cnt);
+        hipLaunchKernelGGL(k_bwd<P>, dim3(nb), dim3(kThreads), smL, st, n, a.bL, h,
+                           hord_offset(nh, h), tb, alpha, R, a.cnt);
         BN_CHECK_LAUNCH();
     }
     rec(4);
+    return launch_gamma_edges<P>(a, L, R, st, ev);
+}
+
+// Gamma (Eq. 12), edges (Eq. 11) and the invariants, after both sweeps.
+template <class P>
+static hipError_t launch_gamma_edges(const LatticeArgs &a, const typename P::Store &L,
+                                     const typename P::Store &R, hipStream_t st,
+                                     PhaseEvents *ev) {
+    using V = typename P::V;
+    const int n = a.n, d = a.d;
+    const int nh = n - a.bL;
+    const Tables &tb = a.tb;
+    V *beta = reinterpret_cast<V *>(a.beta);
+    V *qt = reinterpret_cast<V *>(a.qt);
+    V *Y1 = reinterpret_cast<V *>(a.Y1);
+    V *Y2 = reinterpret_cast<V *>(a.Y2);
+    V *gam = reinterpret_cast<V *>(a.gam);
+    V *part = reinterpret_cast<V *>(a.part);
+    V *layer = reinterpret_cast<V *>(a.layer);
+    auto rec = [&](int idx) {
+        if (ev && ev->ev[idx]) (void)hipEventRecord(ev->ev[idx], st);
+    };
     {
         const GammaGeom &gg = a.gg;
         if (a.bG == 12) {
@@ -2980,6 +3048,86 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     BN_CHECK_LAUNCH();
     rec(6);
     return hipSuccess;
+}
+
+// The FP32-scaled lattice with alpha never materialised: per-node linear
+// scales and bounds, the 9-bit block seeds (timer entries 8 and 9 bracket
+// them), then the fused sweeps, one launch per layer.
+static hipError_t launch_lattice_fused(const LatticeArgs &a, const PolX32::Store &L,
+                                       const PolX32::Store &R, hipStream_t st,
+                                       PhaseEvents *ev) {
+    const int n = a.n;
+    auto rec = [&](int idx) {
+        if (ev && ev->ev[idx]) (void)hipEventRecord(ev->ev[idx], st);
+    };
+    FusedArgs f{};
+    f.n = n;
+    f.d = a.d;
+    f.K = a.K;
+    f.KS = a.KS9;
+    f.offd = host_kcount(n - 1, a.d - 1);
+    f.force_slow = a.lin_mode == 2 ? 1 : 0;
+    f.zw = a.zw9;
+    f.flin = a.flin;
+    f.beta = reinterpret_cast<const X32 *>(a.beta);
+    f.qt = reinterpret_cast<const X32 *>(a.qt);
+    f.betal = a.betal;
+    f.anc = reinterpret_cast<const int *>(a.anc);
+    f.linok = a.linok;
+    f.emax = a.emax;
+    f.nslow = a.fbA;
+    f.glo = a.glo;
+    f.binom = a.tb.binom;
+    f.lorder = a.tb.lorder;
+    f.loff = a.tb.loff;
+    f.hord = a.tb.hord;
+    f.cnt = a.cnt;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_prep_lin<PolX32>), dim3(n), dim3(kThreads), 0, st, n,
+                       a.K, (const X32 *)a.beta, a.betal, (int *)a.anc, a.linok, a.emax);
+    BN_CHECK_LAUNCH();
+    rec(8);
+    // the alpha tiles' seeds by blocks of 13-bit tiles (doubles, linear-scale
+    // nodes), when the grouped kernel applies; the 9-bit seeds come from them
+    const double *zs13 = nullptr;
+    if (a.Zs && a.KS > 0 && a.lin_mode != 2) {
+        const int N = n - 1, d = a.d, hA = N - 13, bS = hA - 4 < 8 ? hA - 4 : 8;
+        const uint32_t nhiMax = bS >= 4 ? host_kcount(hA - bS, d) : 0u;
+        if (bS >= 4 && d <= 7 && (size_t)(d + 1) * nhiMax <= 4096) {
+            const size_t smB = 8 * (4096 + 256) + 33 * 33 * 4 + (size_t)(d + 1) * nhiMax * 4;
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_seeds_blk<PolX32>),
+                               dim3((unsigned)(n << (hA - bS))), dim3(kThreads), smB, st, n, d,
+                               a.K, a.KS, bS, nhiMax, a.tb, (const double *)a.betal,
+                               (const int *)a.linok, a.Zs);
+            BN_CHECK_LAUNCH();
+            zs13 = a.Zs;
+        }
+    }
+    {
+        const hipError_t e = launch_fused_seeds(f, zs13, a.KS, st);
+        if (e != hipSuccess) return e;
+    }
+    rec(9);
+    rec(2);
+    const int nh = n - 9;
+    for (int h = 0; h <= nh; ++h) {
+        const hipError_t e = launch_fused_sweep(f, true, h, a.tiles_per_layer[h], L, st);
+        if (e != hipSuccess) return e;
+    }
+    rec(3);
+    if (a.fwd_only) {
+        hipLaunchKernelGGL(k_log_LV<PolX32>, dim3(1), dim3(64), 0, st, n, L,
+                           (const double *)a.gauge_exp, (const unsigned long long *)a.cnt,
+                           (const uint32_t *)a.fbA, a.diag);
+        BN_CHECK_LAUNCH();
+        rec(6);
+        return hipSuccess;
+    }
+    for (int h = nh; h >= 0; --h) {
+        const hipError_t e = launch_fused_sweep(f, false, h, a.tiles_per_layer[h], R, st);
+        if (e != hipSuccess) return e;
+    }
+    rec(4);
+    return launch_gamma_edges<PolX32>(a, L, R, st, ev);
 }
 
 template hipError_t launch_lattice<PolLog>(const LatticeArgs &, const PolLog::Store &,

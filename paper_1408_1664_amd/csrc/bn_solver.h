@@ -33,6 +33,9 @@ struct Plan {
         o_fbG, o_rtG, o_betal, o_anc, o_linok, o_Zs, o_ps, o_bits;
     uint32_t KS;                  // K(13, d - 1)
     bool alpha_lin;               // linear alpha tiles (seeds in o_Zs)
+    bool fused;                   // alpha never materialised (9-bit block seeds)
+    uint32_t KS9;                 // K(9, d - 1): stored seeds per block
+    size_t o_zw9, o_emax, o_flin, o_hord, o_glo;
     size_t total;
 };
 

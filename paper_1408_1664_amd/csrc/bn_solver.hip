@@ -97,7 +97,10 @@ bn_status validate(const bn_problem *p, bool host_data, bool check_values) {
     return BN_OK;
 }
 
-Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool with_post) {
+// fuse: 1 for the fused sweeps (alpha never materialised), 0 for alpha in
+// HBM, -1 to decide (see make_plan)
+static Plan plan_of(int n, int d_in, int m, bn_precision prec, bool with_data, bool with_post,
+                    int fuse) {
     Plan P{};
     P.n = n;
     P.m = m;
@@ -133,6 +136,11 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
         if (!strcmp(lt, "0")) P.lin_mode = 0;
         else if (!strcmp(lt, "force")) P.lin_mode = 2;
     }
+    // Alpha never materialised (FP32-scaled form with linear tiles on): the
+    // sweeps rebuild alpha from the seeds of 9-bit blocks.
+    P.fused = fuse == 1 && P.x32 && P.lin_mode != 0 && n >= 10;
+    if (P.fused) P.bL = 9;
+    P.KS9 = (P.fused && d > 0) ? (uint32_t)kcount_u64(9, d - 1) : 0;
     P.KG = (uint32_t)kcount_u64(P.bG, d);
     P.KA = (uint32_t)kcount_u64(P.aG, d);
     P.W = std::max(std::max(P.bA, P.bG), P.aG);
@@ -184,6 +192,8 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.o_seedA = take(kcount_u64(P.bA, d) * 4);
     P.o_items = take(kcount_u64(N - P.bA, d) * 4);
     P.o_ordC = take(256);
+    P.o_hord = take(((size_t)4) << (n - P.bL));
+    P.o_glo = take(512 * 4);
     P.o_arity = take(64);
     P.o_rho = take(34 * 8);
     P.o_q = take(32 * 8);
@@ -200,8 +210,8 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.o_scores_end = o;
     P.o_beta = take((size_t)n * P.K * V);
     if (P.x32) {
-        P.o_alpha_f = take((size_t)n * NN * 4);
-        P.o_alpha_b = take((size_t)n * NN);
+        P.o_alpha_f = P.fused ? 0 : take((size_t)n * NN * 4);
+        P.o_alpha_b = P.fused ? 0 : take((size_t)n * NN);
         P.o_L_f = take(NS * 4);
         P.o_L_b = take(NS);
         P.o_R_f = take(NS * 4);
@@ -216,15 +226,23 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     P.o_gam = take((size_t)n * P.K * V);
     P.o_part = take(std::max(((size_t)1 << nh) * (P.bL + 1),
                              n >= 12 ? ((size_t)1 << (n - 12)) * 13 : (size_t)0) * V);
-    P.o_fbA = P.bA == 13 ? take(4 * (1 + ((size_t)n << (N - 13)))) : 0;
-    P.o_betal = P.bA == 13 ? take((size_t)n * P.K * 8) : 0;
+    P.o_fbA = P.fused ? take(8) : (P.bA == 13 ? take(4 * (1 + ((size_t)n << (N - 13)))) : 0);
+    P.o_betal = (P.bA == 13 || P.fused) ? take((size_t)n * P.K * 8) : 0;
     // Linear alpha tiles keep their seeds (K(13, d) doubles per tile) in the
     // workspace when those take at most 16 GiB; otherwise alpha runs in the
     // number system proper.
     P.KS = (P.bA == 13 && d > 0) ? (uint32_t)kcount_u64(13, d - 1) : 0;   // seeds of size < d
     const uint64_t zs_bytes = P.bA == 13 ? ((uint64_t)n << (N - 13)) * P.KS * 8 : 0;
-    P.alpha_lin = P.lin_mode != 0 && P.bA == 13 && zs_bytes <= (16ull << 30);
-    P.o_Zs = P.alpha_lin ? take(zs_bytes) : 0;
+    P.alpha_lin = !P.fused && P.lin_mode != 0 && P.bA == 13 && zs_bytes <= (16ull << 30);
+    // the fused path builds its 9-bit block seeds from the same 13-bit seeds
+    const bool zs13 = P.fused && P.bA == 13 && d > 0 && zs_bytes <= (16ull << 30);
+    P.o_Zs = (P.alpha_lin || zs13) ? take(zs_bytes) : 0;
+    // seeds of the 9-bit blocks: K(9, d - 1) of 8 bytes per block, 2^(n - 10)
+    // blocks per node
+    const uint64_t nz9 = P.fused ? ((uint64_t)n << (N - 9)) * P.KS9 : 0;
+    P.o_zw9 = P.fused ? take(nz9 * 8) : 0;
+    P.o_emax = take(32 * 4);
+    P.o_flin = take(64 * 4);
     P.o_anc = take(32 * 8);
     P.o_linok = take(32 * 4);
     // Gamma lists: endpoints for a second scale (at most one entry per tile and
@@ -237,6 +255,25 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
     if (with_data) P.o_data = take((size_t)n * (size_t)std::max(m, 1));
     P.total = o;
     P.max_bins = 1;
+    return P;
+}
+
+// Materialised alpha costs 2.9x the fused path's HBM footprint but measures
+// faster (n = 30: 103.7 against 120.4 ms; n = 25: 5.6 against 6.9 ms), so
+// the fused sweeps are taken only where alpha would not fit: from n = 23
+// when the materialised workspace exceeds kFuseAboveBytes (a device of
+// 288 GB, less room for the caller's own buffers). BN_FUSED_ALPHA=1 takes
+// the fused path from n = 10, =0 never (tests, measurements).
+static constexpr size_t kFuseAboveBytes = 240ull << 30;
+
+Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool with_post) {
+    if (const char *fa = getenv("BN_FUSED_ALPHA")) {
+        if (!strcmp(fa, "0")) return plan_of(n, d_in, m, prec, with_data, with_post, 0);
+        if (!strcmp(fa, "1")) return plan_of(n, d_in, m, prec, with_data, with_post, 1);
+    }
+    Plan P = plan_of(n, d_in, m, prec, with_data, with_post, 0);
+    if (n >= 23 && P.x32 && P.lin_mode != 0 && P.total > kFuseAboveBytes)
+        P = plan_of(n, d_in, m, prec, with_data, with_post, 1);
     return P;
 }
 
@@ -265,6 +302,7 @@ static Tables tables_of(const Plan &P, char *ws) {
     tb.seedA = reinterpret_cast<uint32_t *>(ws + P.o_seedA);
     tb.items = reinterpret_cast<uint32_t *>(ws + P.o_items);
     tb.ordC = reinterpret_cast<uint8_t *>(ws + P.o_ordC);
+    tb.hord = reinterpret_cast<uint32_t *>(ws + P.o_hord);
     return tb;
 }
 
@@ -341,14 +379,20 @@ static LatticeArgs lattice_args(const Plan &P, char *ws, double *dev_post, doubl
     a.tiles_per_layer = P.tiles.data();
     a.gg = P.gg;
     a.lin_mode = P.lin_mode;
-    a.fbA = P.bA == 13 ? reinterpret_cast<uint32_t *>(ws + P.o_fbA) : nullptr;
+    a.fbA = (P.bA == 13 || P.fused) ? reinterpret_cast<uint32_t *>(ws + P.o_fbA) : nullptr;
     a.fbG = P.bG == 12 ? reinterpret_cast<uint32_t *>(ws + P.o_fbG) : nullptr;
     a.rtG = P.bG == 12 ? reinterpret_cast<uint32_t *>(ws + P.o_rtG) : nullptr;
-    a.betal = P.bA == 13 ? reinterpret_cast<double *>(ws + P.o_betal) : nullptr;
+    a.betal = (P.bA == 13 || P.fused) ? reinterpret_cast<double *>(ws + P.o_betal) : nullptr;
     a.anc = ws + P.o_anc;
     a.linok = reinterpret_cast<int *>(ws + P.o_linok);
-    a.Zs = P.alpha_lin ? reinterpret_cast<double *>(ws + P.o_Zs) : nullptr;
+    a.Zs = P.o_Zs ? reinterpret_cast<double *>(ws + P.o_Zs) : nullptr;
     a.KS = P.KS;
+    a.fused = P.fused ? 1 : 0;
+    a.KS9 = P.KS9;
+    a.zw9 = P.fused ? reinterpret_cast<void *>(ws + P.o_zw9) : nullptr;
+    a.emax = reinterpret_cast<int *>(ws + P.o_emax);
+    a.flin = reinterpret_cast<int *>(ws + P.o_flin);
+    a.glo = reinterpret_cast<uint32_t *>(ws + P.o_glo);
     return a;
 }
 

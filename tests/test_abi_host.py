@@ -55,18 +55,32 @@ def test_num_parent_sets():
     assert bn.num_parent_sets(5, -1) == 0
 
 
-def test_workspace_grows_with_n_and_precision():
+def test_workspace_grows_with_n_and_precision(monkeypatch):
     a = bn.workspace_bytes(20, 3, 500, "fp32")
     b = bn.workspace_bytes(21, 3, 500, "fp32")
     c = bn.workspace_bytes(20, 3, 500, "fp64")
     assert b > 1.9 * a
     assert c > a
-    # dominant terms: alpha n 2^(n-1) and the two 2^n sweeps
+    # dominant terms with alpha materialised: alpha n 2^(n-1) and the two 2^n sweeps
     n = 25
-    w32 = bn.workspace_bytes(n, 4, 2000, "fp32")
-    assert w32 >= 5 * n * 2 ** (n - 1) + 2 * 5 * 2 ** n
     w64 = bn.workspace_bytes(n, 4, 2000, "fp64")
     assert w64 >= 8 * n * 2 ** (n - 1) + 2 * 8 * 2 ** n
+    w32m = bn.workspace_bytes(n, 4, 2000, "fp32")    # the default below 240 GiB
+    assert w32m >= 5 * n * 2 ** (n - 1) + 2 * 5 * 2 ** n
+    monkeypatch.setenv("BN_FUSED_ALPHA", "0")
+    assert bn.workspace_bytes(n, 4, 2000, "fp32") == w32m
+    # alpha never materialised: the two sweeps plus the 9-bit block seeds,
+    # K(9, d - 1) of 8 bytes per block
+    monkeypatch.setenv("BN_FUSED_ALPHA", "1")
+    w32 = bn.workspace_bytes(n, 4, 2000, "fp32")
+    seeds = 8 * n * 2 ** (n - 10) * (1 + 9 + 36 + 84)
+    assert 2 * 5 * 2 ** n + seeds <= w32 < w32m - 5 * n * 2 ** (n - 1) + seeds + (64 << 20)
+    # n = 31 fits one 288 GB device in both FP32-scaled forms, n = 32 does not exist
+    monkeypatch.delenv("BN_FUSED_ALPHA")
+    assert bn.workspace_bytes(31, 3, 500, "fp32") < 240 * 2 ** 30
+    monkeypatch.setenv("BN_FUSED_ALPHA", "1")
+    assert bn.workspace_bytes(31, 3, 500, "fp32") < 100e9
+    monkeypatch.delenv("BN_FUSED_ALPHA")
     with pytest.raises(bn.BnError):
         bn.workspace_bytes(1, 2, 10, "fp32")
     with pytest.raises(bn.BnError):

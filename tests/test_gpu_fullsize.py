@@ -48,13 +48,16 @@ def _bounds(P, d, tol):
     assert np.all(P.sum(axis=0) <= d + d * tol)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
-def test_n25_against_oracle(prec, tol):
+@pytest.mark.parametrize("prec,tol,fused", [("fp64", 1e-10, "0"), ("fp32", 1e-5, "0"),
+                                            ("fp32", 1e-5, "1")])
+def test_n25_against_oracle(prec, tol, fused, monkeypatch):
+    monkeypatch.setenv("BN_FUSED_ALPHA", fused)   # 1: alpha never materialised
     ref = json.load(open(os.path.join(GOLD, "oracle_n25_binary_m2000_d4.json")))
     ds, p = datagen.workload("n25_binary_m2000_d4")
+    print(f"n25 {prec} fused {fused}", flush=True)
     P, diag = _solve_dev(ds, p["d"], prec, p["ess"])
     err = np.abs(P - np.array(ref["post"])).max()
-    print(f"n25 {prec}: max |dP| = {err:.3e}, log L(V) {diag[0]:.6f} vs {ref['log_LV']:.6f}, "
+    print(f"n25 {prec} fused {fused}: max |dP| = {err:.3e}, log L(V) {diag[0]:.6f} vs {ref['log_LV']:.6f}, "
           f"residual {diag[1]:.2e}, saturated {diag[2]:.0f}, flushed {diag[3]:.0f}", flush=True)
     assert err <= tol
     assert abs(diag[0] - ref["log_LV"]) <= 1e-9 * abs(ref["log_LV"])
@@ -62,12 +65,15 @@ def test_n25_against_oracle(prec, tol):
     _bounds(P, p["d"], tol)
 
 
-def test_n30_properties_and_forms_agree():
+@pytest.mark.parametrize("fused", ["0", "1"])
+def test_n30_properties_and_forms_agree(fused, monkeypatch):
+    monkeypatch.setenv("BN_FUSED_ALPHA", fused)   # FP32-scaled form: 1 = alpha never materialised
     ds, p = datagen.workload("n30_binary_m500_d3")
+    print(f"n30 fused {fused}", flush=True)
     P32, g32 = _solve_dev(ds, p["d"], "fp32", p["ess"])
     P64, g64 = _solve_dev(ds, p["d"], "fp64", p["ess"])
     err = np.abs(P32 - P64).max()
-    print(f"n30: max |P32 - P64| = {err:.3e}; log L(V) {g32[0]:.6f} / {g64[0]:.6f}; "
+    print(f"n30 fused {fused}: max |P32 - P64| = {err:.3e}; log L(V) {g32[0]:.6f} / {g64[0]:.6f}; "
           f"residuals {g32[1]:.2e} / {g64[1]:.2e}; fp32 saturated {g32[2]:.0f} "
           f"flushed {g32[3]:.0f}", flush=True)
     assert err <= 1e-5

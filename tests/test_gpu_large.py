@@ -60,16 +60,19 @@ def _bounds(P, d, tol):
     assert np.all(P.sum(axis=0) <= d + d * tol)
 
 
-@pytest.mark.parametrize("prec,tol,lin", [("fp64", 1e-10, None), ("fp32", 1e-5, None),
-                                          ("fp32", 1e-5, "0")])
-def test_n27_prefix_of_n30_against_oracle(prec, tol, lin, monkeypatch):
+@pytest.mark.parametrize("prec,tol,lin,fused", [("fp64", 1e-10, None, "0"),
+                                                ("fp32", 1e-5, None, "0"),
+                                                ("fp32", 1e-5, "0", "0"),
+                                                ("fp32", 1e-5, None, "1")])
+def test_n27_prefix_of_n30_against_oracle(prec, tol, lin, fused, monkeypatch):
     ref = json.load(open(os.path.join(GOLD, "oracle_n30_binary_m500_d3_first27.json")))
     ds, p = datagen.workload("n30_binary_m500_d3")
     k = ref["first_vars"]
     assert k == 27 and ref["m"] == ds.m and ref["d"] == p["d"]
     if lin is not None:
         monkeypatch.setenv("BN_LINEAR_TILES", lin)
-    print(f"n27 {prec} linear tiles {lin or 'on'}", flush=True)
+    monkeypatch.setenv("BN_FUSED_ALPHA", fused)   # 1: alpha never materialised
+    print(f"n27 {prec} linear tiles {lin or 'on'} fused {fused}", flush=True)
     P, diag = _solve_dev(ds.data[:k], ds.arity[:k], p["d"], prec, p["ess"])
     err = np.abs(P - np.array(ref["post"])).max()
     print(f"n27 {prec}: max |dP| = {err:.3e}, log L(V) {diag[0]:.6f} vs {ref['log_LV']:.6f}, "
@@ -80,16 +83,18 @@ def test_n27_prefix_of_n30_against_oracle(prec, tol, lin, monkeypatch):
     _bounds(P, p["d"], tol)
 
 
-@pytest.mark.parametrize("n,prec", [(28, "fp64"), (28, "fp32"), (29, "fp32"), (30, "fp64"),
-                                    (30, "fp32"), (31, "fp32")])
-def test_no_data_closed_form_at_large_n(n, prec):
+@pytest.mark.parametrize("n,prec,fused", [(28, "fp64", "0"), (28, "fp32", "0"), (29, "fp32", "0"),
+                                          (30, "fp64", "0"), (30, "fp32", "0"), (31, "fp32", "0"),
+                                          (30, "fp32", "1"), (31, "fp32", "1")])
+def test_no_data_closed_form_at_large_n(n, prec, fused, monkeypatch):
     d = 3
+    monkeypatch.setenv("BN_FUSED_ALPHA", fused)   # 1: alpha never materialised
     if not _fits(n, d, 0, prec):
         pytest.skip(f"n={n} {prec} workspace does not fit in free device memory")
     rho = [Fraction(1, math.comb(n - 1, k)) for k in range(d + 1)]
     want = float(m0_closed_form(n, d, rho))
     data = np.zeros((n, 0), np.uint8)
-    print(f"m=0 n={n} {prec}", flush=True)
+    print(f"m=0 n={n} {prec} fused {fused}", flush=True)
     P, diag = _solve_dev(data, np.full(n, 2, np.uint8), d, prec)
     tol = 1e-10 if prec == "fp64" else 1e-5
     off = P[~np.eye(n, dtype=bool)]
@@ -101,12 +106,14 @@ def test_no_data_closed_form_at_large_n(n, prec):
     assert diag[1] < (1e-9 if prec == "fp64" else 1e-4)
 
 
-def test_n31_fp32_properties():
+@pytest.mark.parametrize("fused", ["0", "1"])
+def test_n31_fp32_properties(fused, monkeypatch):
     n, m, d = 31, 500, 3
+    monkeypatch.setenv("BN_FUSED_ALPHA", fused)   # 1: alpha never materialised
     if not _fits(n, d, m, "fp32"):
         pytest.skip("n=31 FP32-scaled workspace does not fit in free device memory")
     ds = datagen.random_dag_dataset(n, m, 2, 3, 1.0, seed=31)
-    print("n31 fp32 m=500", flush=True)
+    print(f"n31 fp32 m=500 fused {fused}", flush=True)
     P, diag = _solve_dev(ds.data, ds.arity, d, "fp32")
     print(f"n31 fp32: log L(V) {diag[0]:.6f}, residual {diag[1]:.2e}, saturated {diag[2]:.0f}, "
           f"flushed {diag[3]:.0f}, fallback {diag[7]:.0f}", flush=True)

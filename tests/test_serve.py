@@ -182,6 +182,30 @@ def test_served_equals_alone(tight, monkeypatch):
 
 
 @pytest.mark.gpu
+def test_served_equals_alone_on_the_serving_stream(monkeypatch):
+    """The first 64 requests of the benchmark's serving stream (n in 10..22,
+    m in 100..2000, arity 2 or 3, d = 3, FP32-scaled), submitted at once so
+    that up to 16 overlap on the device: each result equals the same problem
+    solved alone, bit for bit."""
+    monkeypatch.delenv("BN_SERVE_FAKE", raising=False)
+    monkeypatch.delenv("BN_SERVE_FAIL_ALLOC", raising=False)
+    reqs = datagen.serving_stream(64, seed=4)
+    data = [datagen.request_dataset(r) for r in reqs]
+    assert max(r["n"] for r in reqs) >= 20 and max(r["m"] for r in reqs) >= 1500
+    srv = bn.Server(max_active=16)
+    ts = [srv.submit(ds.data, ds.arity, r["d"], precision="fp32", ess=r["ess"])
+          for ds, r in zip(data, reqs)]
+    for ds, r, t in zip(data, reqs, ts):
+        s, post, rep = srv.poll(t, timeout_us=-1)
+        assert s == bn.BN_OK
+        alone, rep1 = bn.edge_posteriors(ds.data, ds.arity, r["d"], precision="fp32",
+                                         ess=r["ess"])
+        assert np.array_equal(post, alone), (r["idx"], r["n"], r["m"])
+        assert rep["log_LV"] == rep1["log_LV"]
+    srv.close()
+
+
+@pytest.mark.gpu
 def test_served_matches_oracle():
     from oracle import oracle as O
     srv = bn.Server(max_active=4)
