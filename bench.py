@@ -206,6 +206,30 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
 
 
+def mfma_experiment(bn, torch):
+    """One in-tile zeta step (4 bits, FP64) as register add steps against the
+    blocked 0/1 contraction on the FP64 matrix cores (bn_zeta4_probe): one
+    HBM pass over 2^28 doubles, then the arithmetic alone (256 repetitions on
+    2^24 doubles held in registers). Each figure is the best of three."""
+    out = {}
+    for label, count, reps in (("hbm_pass", 1 << 28, 1), ("arithmetic", 1 << 24, 256)):
+        x = torch.rand(count, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for method in ("valu", "mfma"):
+            bn.zeta4_probe(x, y, method, reps)               # warm-up
+            ms = min(bn.zeta4_probe(x, y, method, reps) for _ in range(3))
+            # values transformed per second (each value once per repetition)
+            rate = count * reps / (ms * 1e-3)
+            out[f"{label}_{method}"] = dict(ms=ms, values_per_s=rate,
+                                            GBs=16 * count / (ms * 1e-3) / 1e9 if reps == 1
+                                            else None)
+        out[f"{label}_mfma_over_valu_time"] = (out[f"{label}_mfma"]["ms"] /
+                                               out[f"{label}_valu"]["ms"])
+        del x, y
+        torch.cuda.empty_cache()
+    return out
+
+
 def serving(bn, datagen, num=512, check=512):
     """Serving stream: 512 requests, n ~ U{10..22}, m ~ U{100..2000}, arity
     in {2,3}, d = 3, FP32-scaled. Closed-loop saturation first (all requests
@@ -341,6 +365,9 @@ def main():
                     help="only time the generic subset transforms (2^30 doubles) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES (counter calibration) and exit")
+    ap.add_argument("--mfma-experiment", action="store_true",
+                    help="only time one 4-bit zeta step as register adds and as an FP64 "
+                         "matrix-core contraction, and exit")
     ap.add_argument("--source-digest", action="store_true",
                     help="print the kernel-source digest that counter records carry and exit")
     args = ap.parse_args()
@@ -365,6 +392,9 @@ def main():
     torch.cuda.set_device(0)
     if args.subset_only:
         print(json.dumps({"subset_transform": subset_bench(bn, torch, datagen)}), flush=True)
+        return
+    if args.mfma_experiment:
+        print(json.dumps({"zeta4_step": mfma_experiment(bn, torch)}), flush=True)
         return
     head = measure(bn, torch, datagen, args.workload, args.precision, args.steps, args.warmup)
     print(f"# {args.workload} {args.precision}: {head['ms_per_step']:.2f} ms/step, "

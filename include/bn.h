@@ -314,6 +314,29 @@ typedef enum BN_ENUM_BASE {
 bn_status bn_subset_transform(double *dev_x, int32_t nbits, bn_subset_kind kind, int32_t d,
                               void *hip_stream);
 
+/*
+ * Measurement, not a step of the solve: the blocked 0/1 contraction against
+ * the register pass for one in-tile zeta step. For every 16-entry group g of
+ * the device array x (16 * groups doubles), y(g, T) = sum_{S subset T}
+ * x(g, S) over the four low index bits (Def. 1, untruncated), by
+ *   method 0  four add steps over the 16 values one lane holds (the form of
+ *             the library's in-tile passes), groups staged through LDS so
+ *             that loads and stores are coalesced;
+ *   method 1  the 16-column group matrix times the 16 x 16 subset-inclusion
+ *             matrix on the FP64 matrix cores (four 16x16x4 products per 16
+ *             groups).
+ * reps > 1 repeats the arithmetic on values held in registers (method 0
+ * applies the transform reps times in a row, method 1 accumulates reps equal
+ * products), so that large reps times the arithmetic alone; reps = 1 is one
+ * HBM pass and its y is the transform. groups: a multiple of 16 in
+ * 16..2^32; reps in 1..4096. The caller owns x and y (disjoint, device
+ * memory). Blocks until the kernel has finished; *ms receives its time
+ * (HIP events on the stream; NULL: the default stream). BN_EINVAL for NULL
+ * pointers or out-of-range arguments.
+ */
+bn_status bn_zeta4_probe(const double *dev_x, double *dev_y, uint64_t groups, int32_t method,
+                         int32_t reps, void *hip_stream, float *ms);
+
 const char *bn_status_string(bn_status s);
 
 #ifdef __cplusplus

@@ -33,7 +33,8 @@ EXPORTED = ["bn_num_parent_sets", "bn_local_scores", "bn_workspace_bytes",
             "bn_timer_create",
             "bn_timer_destroy", "bn_timer_read", "bn_server_create", "bn_serve_submit",
             "bn_serve_poll", "bn_server_destroy", "bn_subset_transform",
-            "bn_modular_feature_posterior", "bn_status_string", "bn_edge_posteriors_noalloc"]
+            "bn_modular_feature_posterior", "bn_status_string", "bn_edge_posteriors_noalloc",
+            "bn_zeta4_probe"]
 
 # Largest workspace the allocation-free entry point takes (BN_NOALLOC_MAX_BYTES).
 NOALLOC_MAX_BYTES = 256 << 20
@@ -117,6 +118,8 @@ def lib():
         L.bn_modular_feature_posterior.restype = ctypes.c_int
         L.bn_subset_transform.argtypes = [P, I32, ctypes.c_int, I32, P]
         L.bn_subset_transform.restype = ctypes.c_int
+        L.bn_zeta4_probe.argtypes = [P, P, U64, I32, I32, P, P]
+        L.bn_zeta4_probe.restype = ctypes.c_int
         L.bn_status_string.argtypes = [ctypes.c_int]
         L.bn_status_string.restype = ctypes.c_char_p
         _lib = L
@@ -328,6 +331,25 @@ def subset_transform(x_dev, kind: str, d: int = -1, stream=None):
     _check(lib().bn_subset_transform(ctypes.c_void_p(x_dev.data_ptr()), nbits,
                                      SUBSET_KINDS[kind], int(d), ctypes.c_void_p(st)),
            "bn_subset_transform")
+
+
+def zeta4_probe(x_dev, y_dev, method: str, reps: int = 1, stream=None) -> float:
+    """bn_zeta4_probe: the 4-bit upward zeta of every 16-entry group of the
+    float64 device tensor x_dev into y_dev, by "valu" (register add steps) or
+    "mfma" (the group matrix times the subset-inclusion matrix on the FP64
+    matrix cores); reps > 1 repeats the arithmetic in registers. Waits for
+    the kernel and returns its time in ms."""
+    import torch
+
+    for t in (x_dev, y_dev):
+        assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+    assert x_dev.numel() == y_dev.numel() and x_dev.numel() % 16 == 0
+    st = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+    ms = ctypes.c_float(0.0)
+    _check(lib().bn_zeta4_probe(ctypes.c_void_p(x_dev.data_ptr()), ctypes.c_void_p(y_dev.data_ptr()),
+                                x_dev.numel() // 16, {"valu": 0, "mfma": 1}[method], int(reps),
+                                ctypes.c_void_p(st), ctypes.byref(ms)), "bn_zeta4_probe")
+    return float(ms.value)
 
 
 class Server:

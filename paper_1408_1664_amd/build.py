@@ -9,7 +9,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbnpost.so")
-SOURCES = ["bn_kernels.hip", "bn_fused.hip", "bn_solver.hip", "bn_serve.hip", "bn_subset.hip"]
+SOURCES = ["bn_kernels.hip", "bn_fused.hip", "bn_solver.hip", "bn_serve.hip", "bn_subset.hip",
+           "bn_probe.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -21,15 +22,20 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
              "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
 LIB_SAN = os.path.join(HERE, "libbnpost_san.so")
+# Measurement build of the literal block-only FP32 form (every value a plain
+# float under the per-node and per-layer gauges, no per-value exponent);
+# selected with BN_LIBRARY.
+LIB_LITERAL = os.path.join(HERE, "libbnpost_literal.so")
 
 
-def build(verbose: bool = False, sanitize: bool = False) -> str:
+def build(verbose: bool = False, sanitize: bool = False, literal: bool = False) -> str:
     """Compile every source for gfx950 and link libbnpost.so; with sanitize,
     libbnpost_san.so with the host code under ASan and UBSan (loaded with
-    the sanitizer runtime preloaded, BN_LIBRARY pointing at it)."""
+    the sanitizer runtime preloaded, BN_LIBRARY pointing at it); with
+    literal, libbnpost_literal.so (BN_X32_LITERAL)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    flags = FLAGS + (SAN_FLAGS if sanitize else [])
-    out_lib = LIB_SAN if sanitize else LIB
+    flags = FLAGS + (SAN_FLAGS if sanitize else []) + (["-DBN_X32_LITERAL"] if literal else [])
+    out_lib = LIB_SAN if sanitize else (LIB_LITERAL if literal else LIB)
     with tempfile.TemporaryDirectory() as td:
         objs = []
         procs = []
@@ -57,4 +63,4 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True, sanitize="--sanitize" in sys.argv))
+    print(build(verbose=True, sanitize="--sanitize" in sys.argv, literal="--literal" in sys.argv))

@@ -180,6 +180,17 @@ struct PolX32 {
     static constexpr int kBytes = 5;
     __device__ static inline V zero() { return X32{0.0f, kEZero}; }
     __device__ static inline V one() { return X32{1.0f, 0}; }
+#ifdef BN_X32_LITERAL
+    // Measurement build of the literal block-only FP32 form: the exponent
+    // stays 0, so every value is a plain float and only the per-node and
+    // per-layer gauges (applied in FP64 to the log scores) set its range;
+    // values beyond the FP32 range become inf or 0. Used with the linear
+    // tiles off (they would keep the range in doubles).
+    __device__ static inline V norm(V x) {
+        if (!(x.f > 0.0f)) return zero();
+        return X32{ldexpf(x.f, x.e), 0};
+    }
+#else
     // Bring f back into [2^-32, 2^32) (f >= 0, normal or zero).
     __device__ static inline V norm(V x) {
         if (!(x.f > 0.0f)) return zero();
@@ -190,6 +201,7 @@ struct PolX32 {
         x.e += s << 6;
         return x;
     }
+#endif
     __device__ static inline V mul(V a, V b) { return norm(X32{a.f * b.f, a.e + b.e}); }
     // Product without renormalisation (f may leave [2^-32, 2^32); add() stays
     // exact as long as f stays within the FP32 range).
@@ -209,6 +221,9 @@ struct PolX32 {
     __device__ static inline V acc_value(const Acc &a) { return a; }
     __device__ static inline V from_log(double x) {
         if (!(x > -1e300)) return zero();
+#ifdef BN_X32_LITERAL
+        return norm(X32{(float)exp(x), 0});
+#endif
         const double t = x * 1.4426950408889634074;  // log2
         const int e = (int)floor((t + 32.0) / 64.0);
         const float f = (float)exp(x - (double)e * 64.0 * 0.69314718055994530942);

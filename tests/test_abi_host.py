@@ -145,6 +145,22 @@ def test_subset_transform_rejects_bad_arguments():
     assert L.bn_subset_transform(fake, 10, 3, 0, None) == bn.BN_EINVAL
 
 
+def test_zeta4_probe_rejects_bad_arguments():
+    import ctypes
+    L = bn.lib()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails the checks
+    ms = ctypes.c_float()
+    assert L.bn_zeta4_probe(None, fake, 16, 0, 1, None, ctypes.byref(ms)) == bn.BN_EINVAL
+    assert L.bn_zeta4_probe(fake, fake, 16, 0, 1, None, None) == bn.BN_EINVAL
+    assert L.bn_zeta4_probe(fake, fake, 8, 0, 1, None, ctypes.byref(ms)) == bn.BN_EINVAL
+    assert L.bn_zeta4_probe(fake, fake, 40, 1, 1, None, ctypes.byref(ms)) == bn.BN_EINVAL
+    assert L.bn_zeta4_probe(fake, fake, (1 << 32) + 16, 0, 1, None,
+                            ctypes.byref(ms)) == bn.BN_EINVAL
+    assert L.bn_zeta4_probe(fake, fake, 16, 2, 1, None, ctypes.byref(ms)) == bn.BN_EINVAL
+    assert L.bn_zeta4_probe(fake, fake, 16, 0, 0, None, ctypes.byref(ms)) == bn.BN_EINVAL
+    assert L.bn_zeta4_probe(fake, fake, 16, 1, 4097, None, ctypes.byref(ms)) == bn.BN_EINVAL
+
+
 def test_modular_feature_rejects_bad_arguments():
     import ctypes
     data = np.zeros((4, 10), np.uint8)
