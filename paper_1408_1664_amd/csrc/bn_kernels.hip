@@ -74,9 +74,14 @@ static LaneOrder lane_order_c(int d) {
 
 // Tables: binomials, popcount-ordered masks of the sweep tile, patterns of
 // at most d ones (numeric order: the w-bit patterns are exactly the first
-// K(w,d) entries), and the ranked seed masks of the Gamma tile.
+// K(w,d) entries), and the ranked seed masks of the Gamma tile. Every
+// workgroup builds the binomials and layer offsets in LDS; workgroup 0 also
+// stores them; the mask loops are spread over the whole grid.
 __global__ void k_setup(Tables tb, LaneOrder oc, int bL, int W, int bG, int d) {
+    __shared__ uint32_t bn[33 * 33];
+    __shared__ uint32_t loff[34];
     const int t = threadIdx.x;
+    const bool first = blockIdx.x == 0;
     // C(a, b) by the product formula, one entry per thread: after step j the
     // running value is C(a - b + j, j), so every division is exact and no
     // intermediate exceeds 32 * C(32, 16) < 2^35
@@ -84,30 +89,32 @@ __global__ void k_setup(Tables tb, LaneOrder oc, int bL, int W, int bG, int d) {
         const int a = x / 33, b = x % 33;
         uint64_t c = b <= a ? 1u : 0u;
         for (int j = 1; j <= b && b <= a; ++j) c = c * (uint64_t)(a - b + j) / (uint64_t)j;
-        tb.binom[x] = (uint32_t)c;
+        bn[x] = (uint32_t)c;
+        if (first) tb.binom[x] = (uint32_t)c;
     }
     __syncthreads();
-    const uint32_t *bn = tb.binom;
     if (t == 0) {
         uint32_t acc = 0;
         for (int l = 0; l <= bL; ++l) {
-            tb.loff[l] = acc;
+            loff[l] = acc;
             acc += C(bn, bL, l);
         }
-        tb.loff[bL + 1] = acc;
+        loff[bL + 1] = acc;
     }
     __syncthreads();
+    if (first && t <= bL + 1) tb.loff[t] = loff[t];
+    const uint32_t x0 = blockIdx.x * kThreads + t, step = gridDim.x * kThreads;
     // popcount-ordered tile masks: position = offset of the layer + colex rank
-    for (uint32_t x = t; x < (1u << bL); x += kThreads) {
+    for (uint32_t x = x0; x < (1u << bL); x += step) {
         int k = __popc(x);
         uint32_t r = 0;
         int j = 0;
         for (int p = 0; p < bL; ++p)
             if ((x >> p) & 1) r += C(bn, p, ++j);
-        tb.lorder[tb.loff[k] + r] = (uint16_t)x;
+        tb.lorder[loff[k] + r] = (uint16_t)x;
     }
     // patterns with at most d ones over W bits, numeric order
-    for (uint32_t x = t; x < (1u << W); x += kThreads) {
+    for (uint32_t x = x0; x < (1u << W); x += step) {
         int ones = __popc(x);
         if (ones > d) continue;
         uint32_t pos = 0;
@@ -121,9 +128,9 @@ __global__ void k_setup(Tables tb, LaneOrder oc, int bL, int W, int bG, int d) {
         tb.pat[pos] = (uint16_t)x;
     }
     // lane order of the Gamma tile's layout C (lane_order_c)
-    tb.ordC[t] = oc.p[t];
+    if (first) tb.ordC[t] = oc.p[t];
     // ranked seed masks of the Gamma tile (bG bits): size, then colex
-    for (uint32_t x = t; x < (1u << bG); x += kThreads) {
+    for (uint32_t x = x0; x < (1u << bG); x += step) {
         int k = __popc(x);
         if (k > d) continue;
         uint32_t r = Kcount(bn, bG, k - 1);
@@ -250,6 +257,9 @@ __global__ void k_scores(int n, int m, const uint8_t *__restrict__ data,
 // log B_i(G) = log rho(|G|) + log p(x_i|x_G); beta_i = B_i / 2^E_i with
 // E_i = round(max_G log2 B_i(G)) in the scaled form (0 in log form); the same
 // for q(k) with a per-layer exponent F_k.
+// Scores of one row per workgroup row (blockIdx.x = node), kPrepChunk
+// entries per workgroup (blockIdx.y).
+constexpr uint32_t kPrepChunk = 2048;
 template <class P>
 __global__ void k_prep(int n, int d, uint32_t K, const uint32_t *binom,
                        const double *__restrict__ logp, const double *__restrict__ log_rho,
@@ -259,13 +269,15 @@ __global__ void k_prep(int n, int d, uint32_t K, const uint32_t *binom,
                        uint32_t *rtG) {
     __shared__ double red[kThreads];
     const int i = blockIdx.x;
+    const uint32_t chunk = blockIdx.y;      // entries [chunk * kPrepChunk, ...) of row i
     const int t = threadIdx.x;
-    if (i == 0 && t == 0) {
+    if (i == 0 && chunk == 0 && t == 0) {
         if (fbA) fbA[0] = 0;
         if (fbG) fbG[0] = 0;
         if (rtG) rtG[0] = 0;
     }
     const int N = n - 1;
+    // the row's maximum (every chunk of the row reads the whole row)
     double mx = -__builtin_huge_val();
     for (uint32_t r = t; r < K; r += kThreads) {
         int k = 0;
@@ -275,15 +287,16 @@ __global__ void k_prep(int n, int d, uint32_t K, const uint32_t *binom,
     }
     mx = block_reduce(mx, red, [](double a, double b) { return fmax(a, b); });
     const double E = (gauge && mx > -1e300) ? rint(mx * 1.4426950408889634074) : 0.0;
-    for (uint32_t r = t; r < K; r += kThreads) {
+    const uint32_t r1 = min(K, (chunk + 1) * kPrepChunk);
+    for (uint32_t r = chunk * kPrepChunk + t; r < r1; r += kThreads) {
         int k = 0;
         uint32_t off = 0;
         while (k < d && r >= off + C(binom, N, k)) off += C(binom, N, k++);
         double lb = log_rho[k] + logp[(size_t)i * K + r];
         beta[(size_t)i * K + r] = P::from_log(lb - E * 0.69314718055994530942);
     }
-    if (t == 0) gauge_exp[i] = E;
-    if (i == 0) {
+    if (chunk == 0 && t == 0) gauge_exp[i] = E;
+    if (i == 0 && chunk == 0) {
         for (int k = t; k < n; k += kThreads) {
             double lq = log_q[k];
             double F = (gauge && lq > -1e300) ? rint(lq * 1.4426950408889634074) : 0.0;
@@ -1289,8 +1302,11 @@ __device__ inline void cross_terms(const typename P::Store &alpha, const typenam
 }
 
 // ------------------------------------------- a3: forward sweep, one layer
-// Workgroup = tile H with |H| = h (H over the n-bL high bits). Cross-tile
-// terms (i in H) stream contiguous 2^bL blocks of alpha_i and L, four
+// Workgroup = tile H with |H| = h (H over the n-bL high bits), in colex
+// order: consecutive workgroups, which run at the same time on the eight
+// XCDs, take tiles that share most of their L blocks (a mapping that gave
+// each XCD a contiguous eighth of the layer cut the L2 misses by 10% but
+// measured 5% slower). Cross-tile terms (i in H) stream contiguous 2^bL blocks of alpha_i and L, four
 // consecutive entries per thread; in-tile terms (i among the low bits) use
 // the tile's alpha slices staged in LDS and run popcount layer by popcount
 // layer. Requires bL >= 2.
@@ -2341,28 +2357,18 @@ k_gamma_highA(int n, int d, int a, uint32_t KA, GammaGeom gg, Tables tb,
         dst[(((size_t)s * KA + pi) << hB) + Ht] = vec[tb.pat[pi]];
 }
 
-// Level A for a = 12: the same outputs, from a dense downward zeta over the
-// 12 bits in registers (256 threads x 16 entries; bits 0..3, 4..7, 8..11 in
-// three layouts joined through LDS). A needed output (at most d - sigma
-// ones) receives the same additions in the same order as in the truncated
-// pass above, so the two agree exactly; the other entries are computed too
-// and never read. No pattern table, division or skip test per update.
+// Dense downward zeta over 12 bits: src[x], x < 2^12, into vec[padx(x)]
+// (256 threads x 16 entries; bits 0..3, 4..7, 8..11 in three layouts joined
+// through LDS). An entry with at most d - sigma ones receives the same
+// additions in the same order as in the truncated pass of k_gamma_high1 /
+// k_gamma_highA, so the results agree exactly; the other entries are
+// computed too and never read. No pattern table, division or skip test per
+// update. Ends with a barrier.
 template <class P>
-__global__ void __launch_bounds__(kThreads)
-k_gamma_highA12(int n, uint32_t KA, GammaGeom gg, Tables tb,
-                const typename P::V *__restrict__ Y1, typename P::V *__restrict__ Y2) {
+__device__ __forceinline__ void dense_zeta_down12(const typename P::V *__restrict__ src,
+                                                  typename P::V *vec, uint32_t t) {
     using V = typename P::V;
-    constexpr int a = 12, NR = 16;
-    extern __shared__ unsigned char smem[];
-    V *vec = reinterpret_cast<V *>(smem);   // 2^12 entries at padx indices
-    const int v = find_v(gg.blkA, n, blockIdx.x);
-    const uint32_t local = blockIdx.x - gg.blkA[v];
-    const int hv = gg.hv[v];
-    const int hB = hv - a;
-    const uint32_t Ht = local & ((1u << hB) - 1);
-    const uint32_t s = local >> hB;
-    const uint32_t t = threadIdx.x;
-    const V *src = Y1 + gg.y1off[v] + ((size_t)s << hv) + ((size_t)Ht << a);
+    constexpr int NR = 16;
     V g[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) g[r] = src[(t << 4) | r];
@@ -2390,9 +2396,56 @@ k_gamma_highA12(int n, uint32_t KA, GammaGeom gg, Tables tb,
 #pragma unroll
     for (int r = 0; r < NR; ++r) vec[padx((r << 8) | t)] = g[r];
     __syncthreads();
+}
+
+// Level A for a = 12: the outputs of k_gamma_highA from the dense zeta.
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_gamma_highA12(int n, uint32_t KA, GammaGeom gg, Tables tb,
+                const typename P::V *__restrict__ Y1, typename P::V *__restrict__ Y2) {
+    using V = typename P::V;
+    constexpr int a = 12;
+    extern __shared__ unsigned char smem[];
+    V *vec = reinterpret_cast<V *>(smem);   // 2^12 entries at padx indices
+    const int v = find_v(gg.blkA, n, blockIdx.x);
+    const uint32_t local = blockIdx.x - gg.blkA[v];
+    const int hv = gg.hv[v];
+    const int hB = hv - a;
+    const uint32_t Ht = local & ((1u << hB) - 1);
+    const uint32_t s = local >> hB;
+    const uint32_t t = threadIdx.x;
+    dense_zeta_down12<P>(Y1 + gg.y1off[v] + ((size_t)s << hv) + ((size_t)Ht << a), vec, t);
     V *dst = Y2 + gg.y2off[v];
     for (uint32_t pi = t; pi < KA; pi += kThreads)
         dst[(((size_t)s * KA + pi) << hB) + Ht] = vec[padx(tb.pat[pi])];
+}
+
+// One level with hv = 12 (every one-level endpoint when n = 25): the outputs
+// of k_gamma_high1 from the dense zeta.
+template <class P>
+__global__ void __launch_bounds__(kThreads)
+k_gamma_high1_12(int n, int d, uint32_t K, GammaGeom gg, Tables tb,
+                 const typename P::V *__restrict__ Y1, typename P::V *__restrict__ gam) {
+    using V = typename P::V;
+    extern __shared__ unsigned char smem[];
+    V *vec = reinterpret_cast<V *>(smem);   // 2^12 entries at padx indices
+    const int N = n - 1;
+    const int v = find_v(gg.blk1, n, blockIdx.x);
+    const uint32_t s = blockIdx.x - gg.blk1[v];
+    const uint32_t t = threadIdx.x;
+    const uint32_t *bn = tb.binom;
+    const int bv = gg.bv[v];
+    int sigma;
+    uint32_t cl;
+    seed_of(bn, bv, s, &sigma, &cl);
+    const int tr = d - sigma;
+    dense_zeta_down12<P>(Y1 + gg.y1off[v] + ((size_t)s << 12), vec, t);
+    const uint32_t npat = Kcount(bn, 12, d);
+    for (uint32_t idx = t; idx < npat; idx += kThreads) {
+        const uint32_t x = tb.pat[idx];
+        if (__popc(x) > tr) continue;
+        gam[(size_t)v * K + out_rank(bn, N, sigma, cl, x, bv)] = vec[padx(x)];
+    }
 }
 
 // Level B, workgroup (v, seed): for each a-bit pattern p and each output
@@ -2741,8 +2794,10 @@ hipError_t launch_setup(const Tables &tb, int bL, int W, int bG, int bA, int d, 
             for (int d = 0; d <= 8; ++d) o[d] = lane_order_c(d);
         }
     } ord_tables;
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(kThreads), 0, st, tb, ord_tables.o[std::min(std::max(d, 0), 8)],
-                       bL, W, bG, d);
+    // one workgroup per 256 masks of the largest table
+    const int wmax = std::max(std::max(bL, W), bG);
+    hipLaunchKernelGGL(k_setup, dim3(std::max(1, (1 << wmax) / kThreads)), dim3(kThreads), 0, st,
+                       tb, ord_tables.o[std::min(std::max(d, 0), 8)], bL, W, bG, d);
     BN_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_ranked, dim3(((1u << bA) + kThreads - 1) / kThreads), dim3(kThreads),
                        0, st, (const uint32_t *)tb.binom, bA, d, tb.seedA);
@@ -2830,7 +2885,8 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     auto rec = [&](int idx) {
         if (ev && ev->ev[idx]) (void)hipEventRecord(ev->ev[idx], st);
     };
-    hipLaunchKernelGGL(k_prep<P>, dim3(n), dim3(kThreads), 0, st, n, d, a.K,
+    hipLaunchKernelGGL(k_prep<P>, dim3(n, (a.K + kPrepChunk - 1) / kPrepChunk), dim3(kThreads),
+                       0, st, n, d, a.K,
                        (const uint32_t *)tb.binom, (const double *)a.logp,
                        (const double *)a.log_rho, (const double *)a.log_q, a.gauge, beta, qt,
                        a.gauge_exp, a.fbA, a.fbG, a.rtG);
@@ -3002,8 +3058,19 @@ static hipError_t launch_gamma_edges(const LatticeArgs &a, const typename P::Sto
         BN_CHECK_LAUNCH();
         if (!(a.bG == 12 && a.lin_mode)) rec(7);
         if (gg.blk1[n] > 0) {
-            hipLaunchKernelGGL(k_gamma_high1<P>, dim3(gg.blk1[n]), dim3(kThreads),
-                               sizeof(V) << gg.hmax1, st, n, d, a.K, gg, tb, (const V *)Y1, gam);
+            // every one-level endpoint with 12 high bits (n = 25): the dense
+            // form, as for level A
+            bool all12 = std::is_same<P, PolX32>::value;
+            for (int v = 0; v < n && all12; ++v)
+                if (gg.blk1[v + 1] > gg.blk1[v]) all12 = gg.hv[v] == 12;
+            if (all12)
+                hipLaunchKernelGGL(k_gamma_high1_12<P>, dim3(gg.blk1[n]), dim3(kThreads),
+                                   sizeof(V) * (4096 + 256), st, n, d, a.K, gg, tb,
+                                   (const V *)Y1, gam);
+            else
+                hipLaunchKernelGGL(k_gamma_high1<P>, dim3(gg.blk1[n]), dim3(kThreads),
+                                   sizeof(V) << gg.hmax1, st, n, d, a.K, gg, tb, (const V *)Y1,
+                                   gam);
             BN_CHECK_LAUNCH();
         }
         if (gg.blkA[n] > 0) {
