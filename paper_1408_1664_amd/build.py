@@ -53,7 +53,8 @@ def build(verbose: bool = False, sanitize: bool = False, literal: bool = False) 
             if verbose and out.strip():
                 sys.stderr.write(out)
         tmp = out_lib + ".tmp"
-        link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
+        link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread",
+                "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
         if sanitize:
             link += ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
                      "-Xarch_host", "-shared-libsan"]

@@ -10,6 +10,8 @@
 #include <mutex>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/bn.h"
 #include "bn_device.h"
 #include "bn_kernels.h"
@@ -29,6 +31,25 @@ static uint64_t kcount_u64(int w, int t) {
     return s;
 }
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// BN_LOG_LEVEL (read once): 0 or unset, silent; 1, each solve's plan on
+// stderr; 2, also the report of each blocking solve.
+static int log_level() {
+    static const int lv = [] {
+        const char *e = getenv("BN_LOG_LEVEL");
+        return e ? atoi(e) : 0;
+    }();
+    return lv;
+}
+
+// Host-side ranges for a marker trace (rocprofv3 --marker-trace): the
+// enqueue phases of a solve and the wait of the blocking calls.
+struct Range {
+    explicit Range(const char *m) { roctxRangePushA(m); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 // Parameters passed by value to the parameter kernel (host arrays are
 // consumed at launch, so no caller pointer is kept).
@@ -419,10 +440,23 @@ static bn_status run_lattice(const Plan &P, char *ws, const LatticeArgs &a, hipS
 bn_status enqueue_solve(const Plan &P, const bn_problem *p, const uint8_t *dev_data, char *ws,
                         hipStream_t st, double *dev_post, double *dev_diag, PhaseEvents *ev,
                         double *dev_ps) {
+    if (log_level() >= 1)
+        fprintf(stderr,
+                "[bn] solve n=%d m=%d d=%d %s alpha=%s tiles alpha/sweep/gamma=%d/%d/%d "
+                "linear_tiles=%d workspace=%.3f GiB\n",
+                P.n, P.m, P.d, P.x32 ? "fp32_scaled" : "fp64_log",
+                P.fused ? "fused" : "materialised", P.bA, P.bL, P.bG, P.lin_mode,
+                (double)P.total / (double)(1ull << 30));
+    Range r("bn.enqueue_solve");
     if (ev && ev->ev[0]) HIPCHK(hipEventRecord(ev->ev[0], st));
-    bn_status s = enqueue_scores(P, p, dev_data, ws, st);
+    bn_status s;
+    {
+        Range rs("bn.enqueue_scores");
+        s = enqueue_scores(P, p, dev_data, ws, st);
+    }
     if (s != BN_OK) return s;
     const LatticeArgs a = lattice_args(P, ws, dev_post, dev_diag, dev_ps);
+    Range rl("bn.enqueue_lattice");
     return run_lattice(P, ws, a, st, ev);
 }
 
@@ -494,7 +528,10 @@ bn_status edge_posteriors_host(const bn_problem *p, bn_precision prec, double *p
     if (rs == BN_OK &&
         hipMemcpyAsync(diag, dev_diag, 8 * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
         rs = BN_EDEVICE;
-    if (hipStreamSynchronize(st) != hipSuccess) rs = BN_EDEVICE;
+    {
+        Range rw("bn.wait");
+        if (hipStreamSynchronize(st) != hipSuccess) rs = BN_EDEVICE;
+    }
     if (rs == BN_OK && rep) {
         memset(rep, 0, sizeof(*rep));
         rep->log_LV = diag[0];
@@ -513,6 +550,15 @@ bn_status edge_posteriors_host(const bn_problem *p, bn_precision prec, double *p
         rep->ms_gamma = ms[5];
         rep->ms_edges = ms[6];
         rep->ms_total = tot;
+        if (log_level() >= 2)
+            fprintf(stderr,
+                    "[bn] report log_L(V)=%.9f residual=%.3e saturated=%llu flushed=%llu "
+                    "fallback=%llu ms scores/alpha/fwd/bwd/gamma/edges/total="
+                    "%.3f/%.3f/%.3f/%.3f/%.3f/%.3f/%.3f\n",
+                    rep->log_LV, rep->max_invariant_residual,
+                    (unsigned long long)rep->saturated, (unsigned long long)rep->flushed,
+                    (unsigned long long)rep->fallback_tiles, rep->ms_scores, rep->ms_alpha,
+                    rep->ms_fwd, rep->ms_bwd, rep->ms_gamma, rep->ms_edges, rep->ms_total);
     }
     if (timing)
         for (int k = 0; k < 7; ++k) (void)hipEventDestroy(ev.ev[k]);
