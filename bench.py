@@ -301,32 +301,53 @@ def serving(bn, datagen, num=512, check=512):
 
 
 def subset_bench(bn, torch, datagen, nbits=30, steps=5):
-    """Generic subset transforms in place on 2^nbits doubles (8 GiB at 30
-    bits): upward zeta, upward zeta with |S| <= 3, downward zeta, upward
-    Moebius. Each step restores the input (untimed) and times one transform
-    with events on the current stream. Algorithmic bytes: one read and one
-    write of every entry, 16 B per entry."""
-    base = torch.from_numpy(datagen.subset_values(nbits, 30, "uniform")).cuda()
-    xt = torch.empty_like(base)
-    nbytes = 16 * (1 << nbits)
-    out = dict(nbits=nbits, entries=1 << nbits, algorithmic_bytes=nbytes, steps=steps,
-               passes=1 + max(0, math.ceil((nbits - 12) / 6)), kinds={})
-    for kind, d in [("zeta_up", -1), ("zeta_up", 3), ("zeta_down", -1), ("mobius_up", -1)]:
+    """Generic subset transforms in place on 2^nbits entries: FP64 (8 GiB at
+    30 bits: upward zeta, upward zeta with |S| <= 3, downward zeta, upward
+    Moebius) and the FP32-scaled storage (5 GiB: the zeta kinds). Each step
+    restores the input (untimed) and times one transform with events on the
+    current stream. Algorithmic bytes: one read and one write of every entry
+    (16 B per entry in FP64, 10 B in the FP32-scaled form); the kernels make
+    `passes` such sweeps over the array, so the bytes they move are passes
+    times that."""
+    passes = 1 + max(0, math.ceil((nbits - 12) / 9))
+    out = dict(nbits=nbits, entries=1 << nbits, steps=steps, passes=passes, fp64={}, x32={})
+
+    def timed(call, restore):
         tot = 0.0
         for k in range(steps + 1):
-            xt.copy_(base)
+            restore()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            bn.subset_transform(xt, kind, d)
+            call()
             e1.record()
             e1.synchronize()
             if k > 0:     # the first call is a warmup
                 tot += e0.elapsed_time(e1)
-        ms = tot / steps
-        gbs = nbytes / (ms * 1e-3) / 1e9
-        out["kinds"][f"{kind}" + (f"_d{d}" if d >= 0 else "")] = dict(
-            ms=ms, GB_s=gbs, frac_of_one_pass=gbs / HBM_PEAK_GBS)
+        return tot / steps
+
+    def entry(ms, per_entry):
+        alg = per_entry * (1 << nbits)
+        return dict(ms=ms, algorithmic_bytes=alg, GB_s=alg / (ms * 1e-3) / 1e9,
+                    frac=alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    moved_GB_s=passes * alg / (ms * 1e-3) / 1e9)
+
+    base = torch.from_numpy(datagen.subset_values(nbits, 30, "uniform")).cuda()
+    xt = torch.empty_like(base)
+    for kind, d in [("zeta_up", -1), ("zeta_up", 3), ("zeta_down", -1), ("mobius_up", -1)]:
+        ms = timed(lambda: bn.subset_transform(xt, kind, d), lambda: xt.copy_(base))
+        out["fp64"][f"{kind}" + (f"_d{d}" if d >= 0 else "")] = entry(ms, 16)
     del base, xt
+    torch.cuda.empty_cache()
+    f = torch.empty(1 << nbits, dtype=torch.float32, device="cuda")
+    b = torch.empty(1 << nbits, dtype=torch.uint8, device="cuda")
+
+    def restore_x32():
+        f.fill_(1.5)
+        b.fill_(200)
+    for kind, d in [("zeta_up", -1), ("zeta_up", 3), ("zeta_down", -1)]:
+        ms = timed(lambda: bn.subset_transform_x32(f, b, kind, d), restore_x32)
+        out["x32"][f"{kind}" + (f"_d{d}" if d >= 0 else "")] = entry(ms, 10)
+    del f, b
     torch.cuda.empty_cache()
     return out
 
@@ -424,9 +445,9 @@ def main():
     sub = None
     if not args.no_subset:
         sub = subset_bench(bn, torch, datagen)
-        print(f"# subset transforms 2^30: " + ", ".join(f"{k} {v['ms']:.2f} ms"
-                                                        for k, v in sub["kinds"].items()),
-              file=sys.stderr, flush=True)
+        print(f"# subset transforms 2^30: " + ", ".join(
+            f"{form} {k} {v['ms']:.2f} ms" for form in ("fp64", "x32") for k, v in sub[form].items()),
+            file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(datagen, args.workload, args.cpu_sample_n)

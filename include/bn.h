@@ -337,6 +337,26 @@ bn_status bn_subset_transform(double *dev_x, int32_t nbits, bn_subset_kind kind,
 bn_status bn_zeta4_probe(const double *dev_x, double *dev_y, uint64_t groups, int32_t method,
                          int32_t reps, void *hip_stream, float *ms);
 
+/*
+ * The zeta transforms of bn_subset_transform (BN_ZETA_UP, truncated when
+ * 0 <= d < nbits, Def. 1 and Alg. 2; BN_ZETA_DOWN, Def. 2 and Alg. 3) on
+ * non-negative values in the library's FP32-scaled storage, in place: entry
+ * S is dev_f[S] * 2^(64 * (dev_b[S] - 200)), dev_b[S] = 0 meaning 0; both
+ * planes hold 2^nbits entries (5 bytes per entry instead of 8). Negative
+ * significands are taken as 0 (the number system has no sign), so the
+ * Moebius kinds are not offered (BN_EINVAL). Each add aligns the smaller
+ * operand to the larger exponent by an exact power of two and rounds to
+ * FP32, so an output's relative error is at most about nbits * 2^-24 plus
+ * terms below 2^-64 of the output. Outputs beyond the byte's range are
+ * clamped and counted: dev_counts (NULL: not counted; else two device
+ * uint64) receives += saturations in [0] and flushes of nonzero values to 0
+ * in [1]. Enqueued on the stream (NULL: the default stream); returns without
+ * waiting. nbits in 1..32; BN_EINVAL for NULL planes or nbits out of range.
+ */
+bn_status bn_subset_transform_x32(float *dev_f, uint8_t *dev_b, int32_t nbits,
+                                  bn_subset_kind kind, int32_t d,
+                                  unsigned long long *dev_counts, void *hip_stream);
+
 const char *bn_status_string(bn_status s);
 
 #ifdef __cplusplus

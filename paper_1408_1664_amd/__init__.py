@@ -34,7 +34,7 @@ EXPORTED = ["bn_num_parent_sets", "bn_local_scores", "bn_workspace_bytes",
             "bn_timer_destroy", "bn_timer_read", "bn_server_create", "bn_serve_submit",
             "bn_serve_poll", "bn_server_destroy", "bn_subset_transform",
             "bn_modular_feature_posterior", "bn_status_string", "bn_edge_posteriors_noalloc",
-            "bn_zeta4_probe"]
+            "bn_zeta4_probe", "bn_subset_transform_x32"]
 
 # Largest workspace the allocation-free entry point takes (BN_NOALLOC_MAX_BYTES).
 NOALLOC_MAX_BYTES = 256 << 20
@@ -118,6 +118,8 @@ def lib():
         L.bn_modular_feature_posterior.restype = ctypes.c_int
         L.bn_subset_transform.argtypes = [P, I32, ctypes.c_int, I32, P]
         L.bn_subset_transform.restype = ctypes.c_int
+        L.bn_subset_transform_x32.argtypes = [P, P, I32, ctypes.c_int, I32, P, P]
+        L.bn_subset_transform_x32.restype = ctypes.c_int
         L.bn_zeta4_probe.argtypes = [P, P, U64, I32, I32, P, P]
         L.bn_zeta4_probe.restype = ctypes.c_int
         L.bn_status_string.argtypes = [ctypes.c_int]
@@ -331,6 +333,33 @@ def subset_transform(x_dev, kind: str, d: int = -1, stream=None):
     _check(lib().bn_subset_transform(ctypes.c_void_p(x_dev.data_ptr()), nbits,
                                      SUBSET_KINDS[kind], int(d), ctypes.c_void_p(st)),
            "bn_subset_transform")
+
+
+def subset_transform_x32(f_dev, b_dev, kind: str, d: int = -1, counts_dev=None, stream=None):
+    """In-place zeta transform ("zeta_up", truncated to |S| <= d when
+    0 <= d < nbits, or "zeta_down") of 2^nbits non-negative values in the
+    FP32-scaled storage: value = f * 2^(64 (b - 200)), b = 0 meaning 0
+    (bn_subset_transform_x32). f_dev: float32 device tensor, b_dev: uint8
+    device tensor of the same length; counts_dev: optional int64 device
+    tensor of 2 entries that receives += (saturated, flushed). Enqueued on
+    `stream` (default the current stream); returns without synchronising."""
+    import torch
+
+    assert f_dev.dtype == torch.float32 and f_dev.is_cuda and f_dev.is_contiguous()
+    assert b_dev.dtype == torch.uint8 and b_dev.is_cuda and b_dev.is_contiguous()
+    size = f_dev.numel()
+    nbits = size.bit_length() - 1
+    if size < 2 or size != 1 << nbits or b_dev.numel() != size:
+        raise ValueError("both planes must hold 2^nbits values, nbits >= 1")
+    cnt = None
+    if counts_dev is not None:
+        assert counts_dev.dtype == torch.int64 and counts_dev.is_cuda and counts_dev.numel() == 2
+        cnt = ctypes.c_void_p(counts_dev.data_ptr())
+    st = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+    _check(lib().bn_subset_transform_x32(ctypes.c_void_p(f_dev.data_ptr()),
+                                         ctypes.c_void_p(b_dev.data_ptr()), nbits,
+                                         SUBSET_KINDS[kind], int(d), cnt, ctypes.c_void_p(st)),
+           "bn_subset_transform_x32")
 
 
 def zeta4_probe(x_dev, y_dev, method: str, reps: int = 1, stream=None) -> float:

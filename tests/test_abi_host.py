@@ -145,6 +145,19 @@ def test_subset_transform_rejects_bad_arguments():
     assert L.bn_subset_transform(fake, 10, 3, 0, None) == bn.BN_EINVAL
 
 
+def test_subset_transform_x32_rejects_bad_arguments():
+    import ctypes
+    L = bn.lib()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails the checks
+    assert L.bn_subset_transform_x32(None, fake, 10, 0, -1, None, None) == bn.BN_EINVAL
+    assert L.bn_subset_transform_x32(fake, None, 10, 0, -1, None, None) == bn.BN_EINVAL
+    assert L.bn_subset_transform_x32(fake, fake, 0, 0, -1, None, None) == bn.BN_EINVAL
+    assert L.bn_subset_transform_x32(fake, fake, 33, 1, -1, None, None) == bn.BN_EINVAL
+    assert L.bn_subset_transform_x32(fake, fake, 10, 2, -1, None, None) == bn.BN_EINVAL  # Moebius
+    assert L.bn_subset_transform_x32(fake, fake, 10, 3, -1, None, None) == bn.BN_EINVAL
+    assert L.bn_subset_transform_x32(fake, fake, 10, 4, -1, None, None) == bn.BN_EINVAL
+
+
 def test_zeta4_probe_rejects_bad_arguments():
     import ctypes
     L = bn.lib()
