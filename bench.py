@@ -386,6 +386,8 @@ def main():
                     help="only time the generic subset transforms (2^30 doubles) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES (counter calibration) and exit")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only run the 512-request serving stream and exit")
     ap.add_argument("--mfma-experiment", action="store_true",
                     help="only time one 4-bit zeta step as register adds and as an FP64 "
                          "matrix-core contraction, and exit")
@@ -416,6 +418,9 @@ def main():
         return
     if args.mfma_experiment:
         print(json.dumps({"zeta4_step": mfma_experiment(bn, torch)}), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving(bn, datagen)}), flush=True)
         return
     head = measure(bn, torch, datagen, args.workload, args.precision, args.steps, args.warmup)
     print(f"# {args.workload} {args.precision}: {head['ms_per_step']:.2f} ms/step, "

@@ -72,115 +72,120 @@ static LaneOrder lane_order_c(int d) {
     return o;
 }
 
-// Tables: binomials, popcount-ordered masks of the sweep tile, patterns of
-// at most d ones (numeric order: the w-bit patterns are exactly the first
-// K(w,d) entries), and the ranked seed masks of the Gamma tile. Every
-// workgroup builds the binomials and layer offsets in LDS; workgroup 0 also
-// stores them; the mask loops are spread over the whole grid.
-__global__ void k_setup(Tables tb, LaneOrder oc, int bL, int W, int bG, int d) {
-    __shared__ uint32_t bn[33 * 33];
-    __shared__ uint32_t loff[34];
-    const int t = threadIdx.x;
-    const bool first = blockIdx.x == 0;
-    // C(a, b) by the product formula, one entry per thread: after step j the
-    // running value is C(a - b + j, j), so every division is exact and no
-    // intermediate exceeds 32 * C(32, 16) < 2^35
-    for (int x = t; x < 33 * 33; x += kThreads) {
-        const int a = x / 33, b = x % 33;
-        uint64_t c = b <= a ? 1u : 0u;
-        for (int j = 1; j <= b && b <= a; ++j) c = c * (uint64_t)(a - b + j) / (uint64_t)j;
-        bn[x] = (uint32_t)c;
-        if (first) tb.binom[x] = (uint32_t)c;
+// C(a, b) for a, b <= 32, built at compile time (row by row, Pascal's rule)
+// and read from constant memory by the table kernel.
+struct BinomTable {
+    uint32_t v[33 * 33];
+};
+static constexpr BinomTable make_binom() {
+    BinomTable t{};
+    for (int a = 0; a <= 32; ++a) {
+        t.v[a * 33] = 1;
+        for (int b = 1; b <= a; ++b)
+            t.v[a * 33 + b] = t.v[(a - 1) * 33 + b - 1] + (b < a ? t.v[(a - 1) * 33 + b] : 0u);
     }
-    __syncthreads();
-    if (t == 0) {
-        uint32_t acc = 0;
-        for (int l = 0; l <= bL; ++l) {
-            loff[l] = acc;
-            acc += C(bn, bL, l);
-        }
-        loff[bL + 1] = acc;
-    }
-    __syncthreads();
-    if (first && t <= bL + 1) tb.loff[t] = loff[t];
-    const uint32_t x0 = blockIdx.x * kThreads + t, step = gridDim.x * kThreads;
-    // popcount-ordered tile masks: position = offset of the layer + colex rank
-    for (uint32_t x = x0; x < (1u << bL); x += step) {
-        int k = __popc(x);
-        uint32_t r = 0;
-        int j = 0;
-        for (int p = 0; p < bL; ++p)
-            if ((x >> p) & 1) r += C(bn, p, ++j);
-        tb.lorder[loff[k] + r] = (uint16_t)x;
-    }
-    // patterns with at most d ones over W bits, numeric order
-    for (uint32_t x = x0; x < (1u << W); x += step) {
-        int ones = __popc(x);
-        if (ones > d) continue;
-        uint32_t pos = 0;
-        int above = 0;
-        for (int p = W - 1; p >= 0; --p) {
-            if ((x >> p) & 1) {
-                if (d - above >= 0) pos += Kcount(bn, p, d - above);
-                ++above;
-            }
-        }
-        tb.pat[pos] = (uint16_t)x;
-    }
-    // lane order of the Gamma tile's layout C (lane_order_c)
-    if (first) tb.ordC[t] = oc.p[t];
-    // ranked seed masks of the Gamma tile (bG bits): size, then colex
-    for (uint32_t x = x0; x < (1u << bG); x += step) {
-        int k = __popc(x);
-        if (k > d) continue;
-        uint32_t r = Kcount(bn, bG, k - 1);
-        int j = 0;
-        for (int p = 0; p < bG; ++p)
-            if ((x >> p) & 1) r += C(bn, p, ++j);
-        tb.seedmask[r] = x;
-    }
+    return t;
 }
+static_assert(make_binom().v[5 * 33 + 2] == 10u && make_binom().v[32 * 33 + 16] == 601080390u &&
+                  make_binom().v[32 * 33 + 32] == 1u && make_binom().v[3 * 33 + 5] == 0u,
+              "binomial table");
+__constant__ BinomTable kBinomTab = make_binom();
 
-// Masks over w bits with at most d ones, ranked by size then colex order
-// (numeric order within a size). The w'-bit masks of size s, w' <= w, are the
-// first C(w', s) entries of the size-s section.
-__global__ void k_ranked(const uint32_t *binom, int w, int d, uint32_t *out) {
-    const uint32_t x = blockIdx.x * kThreads + threadIdx.x;
+// Masks over w bits with at most d ones (every mask when d >= w), ranked by
+// size then colex order (numeric order within a size): out[rank] = mask, for
+// the masks x in [x0, x0 + 256).
+__device__ inline void ranked_chunk(const uint32_t *bn, int w, int d, uint32_t x,
+                                    uint32_t *out) {
     if (x >= (1u << w)) return;
     const int k = __popc(x);
     if (k > d) return;
-    uint32_t r = Kcount(binom, w, k - 1);
+    uint32_t r = Kcount(bn, w, k - 1);
     int j = 0;
     for (int p = 0; p < w; ++p)
-        if ((x >> p) & 1) r += C(binom, p, ++j);
+        if ((x >> p) & 1) r += C(bn, p, ++j);
     out[r] = x;
 }
 
-// Masks over w bits by popcount, then colex order (the sweep tiles' high
-// parts, so that a workgroup reads its tile's mask instead of unranking it).
-__global__ void k_hiorder(const uint32_t *binom, int w, uint32_t *out) {
-    const uint32_t x = blockIdx.x * kThreads + threadIdx.x;
-    if (x >> w) return;
-    const int k = __popc(x);
-    uint32_t r = Kcount(binom, w, k - 1);
-    int j = 0;
-    for (int p = 0; p < w; ++p)
-        if ((x >> p) & 1) r += C(binom, p, ++j);
-    out[r] = x;
-}
-
-// Compressed parent-set masks in rank order, K(N,d) of them.
-__global__ void k_famask(const uint32_t *binom, int N, int d, uint32_t K, uint32_t *famask) {
-    uint32_t r = blockIdx.x * kThreads + threadIdx.x;
-    if (r >= K) return;
-    int k = 0;
-    uint32_t off = 0;
-    while (k < d && r >= off + C(binom, N, k)) off += C(binom, N, k++);
-    int pos[32];
-    colex_unrank(binom, r - off, k, pos);
-    uint32_t msk = 0;
-    for (int t = 0; t < k; ++t) msk |= 1u << pos[t];
-    famask[r] = msk;
+// Every per-problem table in one launch; the grid is split into ranges of
+// workgroups, one range per table (TableGrid), all reading the binomials
+// from constant memory:
+//   binomials, layer offsets and popcount-ordered masks of the sweep tile,
+//   patterns of at most d ones over W bits (numeric order: the w-bit
+//   patterns are exactly the first K(w, d) entries), the lane order of the
+//   Gamma tile's layout C and its ranked seed masks (range S);
+//   the alpha tile's ranked seed masks over bA bits (range A);
+//   the ranked high-bit items of an alpha tile over n - 1 - bA bits (I);
+//   the compressed parent-set masks in rank order, K(n - 1, d) (F);
+//   the sweep tiles' high parts over n - bL bits by popcount, then colex (H).
+struct TableGrid {
+    uint32_t s, a, i, f, h;   // cumulative ends of the ranges
+};
+__global__ void k_tables(Tables tb, LaneOrder oc, TableGrid g, int bL, int W, int bG, int bA,
+                         int d, int N, uint32_t K) {
+    const uint32_t *bn = kBinomTab.v;
+    const uint32_t blk = blockIdx.x;
+    const int t = threadIdx.x;
+    if (blk < g.s) {
+        __shared__ uint32_t loff[34];
+        if (blk == 0)
+            for (int x = t; x < 33 * 33; x += kThreads) tb.binom[x] = bn[x];
+        if (t == 0) {
+            uint32_t acc = 0;
+            for (int l = 0; l <= bL; ++l) {
+                loff[l] = acc;
+                acc += C(bn, bL, l);
+            }
+            loff[bL + 1] = acc;
+        }
+        __syncthreads();
+        if (blk == 0 && t <= bL + 1) tb.loff[t] = loff[t];
+        const uint32_t x0 = blk * kThreads + t, step = g.s * kThreads;
+        // popcount-ordered tile masks: position = offset of the layer + colex rank
+        for (uint32_t x = x0; x < (1u << bL); x += step) {
+            int k = __popc(x);
+            uint32_t r = 0;
+            int j = 0;
+            for (int p = 0; p < bL; ++p)
+                if ((x >> p) & 1) r += C(bn, p, ++j);
+            tb.lorder[loff[k] + r] = (uint16_t)x;
+        }
+        // patterns with at most d ones over W bits, numeric order
+        for (uint32_t x = x0; x < (1u << W); x += step) {
+            int ones = __popc(x);
+            if (ones > d) continue;
+            uint32_t pos = 0;
+            int above = 0;
+            for (int p = W - 1; p >= 0; --p) {
+                if ((x >> p) & 1) {
+                    if (d - above >= 0) pos += Kcount(bn, p, d - above);
+                    ++above;
+                }
+            }
+            tb.pat[pos] = (uint16_t)x;
+        }
+        // lane order of the Gamma tile's layout C (lane_order_c)
+        if (blk == 0) tb.ordC[t] = oc.p[t];
+        // ranked seed masks of the Gamma tile (bG bits): size, then colex
+        for (uint32_t x = x0; x < (1u << bG); x += step) ranked_chunk(bn, bG, d, x, tb.seedmask);
+    } else if (blk < g.a) {
+        ranked_chunk(bn, bA, d, (blk - g.s) * kThreads + t, tb.seedA);
+    } else if (blk < g.i) {
+        ranked_chunk(bn, N - bA, d, (blk - g.a) * kThreads + t, tb.items);
+    } else if (blk < g.f) {
+        // compressed parent-set masks in rank order
+        const uint32_t r = (blk - g.i) * kThreads + t;
+        if (r >= K) return;
+        int k = 0;
+        uint32_t off = 0;
+        while (k < d && r >= off + C(bn, N, k)) off += C(bn, N, k++);
+        int pos[32];
+        colex_unrank(bn, r - off, k, pos);
+        uint32_t msk = 0;
+        for (int q = 0; q < k; ++q) msk |= 1u << pos[q];
+        tb.famask[r] = msk;
+    } else {
+        ranked_chunk(bn, N + 1 - bL, 64, (blk - g.f) * kThreads + t, tb.hord);
+    }
 }
 
 // ------------------------------------------------------ a1: local scores
@@ -251,6 +256,78 @@ __global__ void k_scores(int n, int m, const uint8_t *__restrict__ data,
     }
     double tot = block_reduce(acc, red, [](double a, double b) { return a + b; });
     if (t == 0) out[fam] = tot;
+}
+
+// The same scores, four families per workgroup, one wave each, for
+// histograms of at most kScoreWaveBins bins (every family of the problem):
+// a quarter of the workgroups and no workgroup barriers. Parents, counts and
+// the wave's sum stay within the wave (LDS accesses of one wave run in
+// order; the wave barriers keep the compiler from moving them).
+constexpr int kScoreWaveBins = 2048;
+__global__ void __launch_bounds__(kThreads)
+k_scores_w(int n, int m, const uint8_t *__restrict__ data, const uint8_t *__restrict__ arity,
+           uint32_t K, int kind, double ess, const uint32_t *__restrict__ famask, int max_bins,
+           double *__restrict__ out) {
+    extern __shared__ int hist_all[];
+    __shared__ int par_all[4][32];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const uint32_t fam = blockIdx.x * 4u + (uint32_t)w;
+    if (fam >= (uint32_t)n * K) return;          // whole waves
+    int *hist = hist_all + w * max_bins;
+    int *par = par_all[w];
+    const int i = fam / K;
+    const uint32_t msk = famask[fam % K];
+    // parents in mixed-radix order: the highest variable index is the most
+    // significant digit; lane p < 31 tests bit 30 - p
+    const bool has = l < 31 && ((msk >> (30 - l)) & 1);
+    const uint64_t ball = __ballot(has);
+    const int np = __popcll(ball);
+    if (has) {
+        const int p = 30 - l;
+        par[__popcll(ball & ((1ull << l) - 1))] = p < i ? p : p + 1;
+    }
+    __builtin_amdgcn_wave_barrier();
+    int q = 1;
+    for (int p = 0; p < np; ++p) q *= arity[par[p]];
+    const int ri = arity[i];
+    const int bins = q * ri;
+    for (int b = l; b < bins; b += 64) hist[b] = 0;
+    __builtin_amdgcn_wave_barrier();
+    const uint8_t *xi = data + (size_t)i * m;
+    for (int s = l; s < m; s += 64) {
+        int key = 0;
+        for (int p = 0; p < np; ++p) {
+            const int var = par[p];
+            key = key * arity[var] + data[(size_t)var * m + s];
+        }
+        const int bin = key * ri + xi[s];
+        if (bin < bins) atomicAdd(&hist[bin], 1);  // values >= arity are ignored
+    }
+    __builtin_amdgcn_wave_barrier();
+    double a_j, a_jk;
+    if (kind == 0) {
+        a_j = ess / q;
+        a_jk = ess / ((double)q * ri);
+    } else {
+        a_j = ri;
+        a_jk = 1.0;
+    }
+    const double lg_aj = lgamma(a_j), lg_ajk = lgamma(a_jk);
+    double acc = 0.0;
+    for (int j = l; j < q; j += 64) {
+        int nj = 0;
+        double sj = 0.0;
+        for (int k = 0; k < ri; ++k) {
+            const int c = hist[j * ri + k];
+            if (c) {
+                sj += lgamma(a_jk + c) - lg_ajk;
+                nj += c;
+            }
+        }
+        if (nj) acc += sj + lg_aj - lgamma(a_j + nj);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (l == 0) out[fam] = acc;
 }
 
 // ----------------------------------------------- prep: prior and gauges
@@ -2794,24 +2871,17 @@ hipError_t launch_setup(const Tables &tb, int bL, int W, int bG, int bA, int d, 
             for (int d = 0; d <= 8; ++d) o[d] = lane_order_c(d);
         }
     } ord_tables;
-    // one workgroup per 256 masks of the largest table
+    auto blocks = [](uint64_t count) { return (uint32_t)((count + kThreads - 1) / kThreads); };
+    // range S: one workgroup per 256 masks of its largest table
     const int wmax = std::max(std::max(bL, W), bG);
-    hipLaunchKernelGGL(k_setup, dim3(std::max(1, (1 << wmax) / kThreads)), dim3(kThreads), 0, st,
-                       tb, ord_tables.o[std::min(std::max(d, 0), 8)], bL, W, bG, d);
-    BN_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_ranked, dim3(((1u << bA) + kThreads - 1) / kThreads), dim3(kThreads),
-                       0, st, (const uint32_t *)tb.binom, bA, d, tb.seedA);
-    BN_CHECK_LAUNCH();
-    const int hA = (int)N - bA;
-    hipLaunchKernelGGL(k_ranked, dim3(((1u << hA) + kThreads - 1) / kThreads), dim3(kThreads),
-                       0, st, (const uint32_t *)tb.binom, hA, d, tb.items);
-    BN_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_famask, dim3((K + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
-                       (const uint32_t *)tb.binom, (int)N, d, K, tb.famask);
-    BN_CHECK_LAUNCH();
-    const int nh = (int)N + 1 - bL;
-    hipLaunchKernelGGL(k_hiorder, dim3(((1u << nh) + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                       st, (const uint32_t *)tb.binom, nh, tb.hord);
+    TableGrid g;
+    g.s = std::max(1, (1 << wmax) / kThreads);
+    g.a = g.s + blocks(1ull << bA);
+    g.i = g.a + blocks(1ull << (N - bA));
+    g.f = g.i + blocks(K);
+    g.h = g.f + blocks(1ull << (N + 1 - bL));
+    hipLaunchKernelGGL(k_tables, dim3(g.h), dim3(kThreads), 0, st, tb,
+                       ord_tables.o[std::min(std::max(d, 0), 8)], g, bL, W, bG, bA, d, (int)N, K);
     BN_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -2843,9 +2913,14 @@ hipError_t launch_scores(int n, int m, const uint8_t *data, const uint8_t *arity
         BN_CHECK_LAUNCH();
         return hipSuccess;
     }
-    hipLaunchKernelGGL(k_scores, dim3((unsigned)(n * K)), dim3(kThreads),
-                       (size_t)max_bins * sizeof(int), st, n, m, data, arity, K, kind, ess,
-                       famask, out);
+    if (max_bins <= kScoreWaveBins)
+        hipLaunchKernelGGL(k_scores_w, dim3((unsigned)((n * (uint64_t)K + 3) / 4)), dim3(kThreads),
+                           (size_t)4 * max_bins * sizeof(int), st, n, m, data, arity, K, kind, ess,
+                           famask, max_bins, out);
+    else
+        hipLaunchKernelGGL(k_scores, dim3((unsigned)(n * K)), dim3(kThreads),
+                           (size_t)max_bins * sizeof(int), st, n, m, data, arity, K, kind, ess,
+                           famask, out);
     BN_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -144,7 +144,9 @@ static Plan plan_of(int n, int d_in, int m, bn_precision prec, bool with_data, b
         int v[4] = {P.bA, P.bL, P.bG, P.aG};
         if (sscanf(tb, "%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3]) == 4) {
             (void)v[0];
-            P.bL = std::max(2, std::min(v[1], n));
+            // at most 11 sweep bits: the in-tile alpha slices (bL 2^(bL-1)
+            // entries) and the tile must fit the 160 KB of LDS
+            P.bL = std::max(2, std::min(std::min(v[1], n), 11));
             (void)v[2];
             P.aG = std::max(1, std::min(v[3], 12));
         }
