@@ -31,6 +31,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <iterator>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -89,16 +90,123 @@ class Executor {
     bool alloc_fails() { return ++allocs == fail_at; }
 };
 
+// ------------------------------------------------------------ device arena
+// Workspaces of the requests come from chunks of device memory that the
+// server allocates rarely and keeps: hipMalloc per request costs more than a
+// small solve (and serialises the worker), hipFree synchronises the whole
+// device. A chunk is kChunk bytes (or the request's size when larger),
+// and the chunks together stay within the memory budget (limit); their free
+// ranges (offset -> length, multiples of the 2 MiB granule) are kept
+// coalesced, and a request takes the smallest free range that fits (best
+// fit over every chunk). When no range fits, a new chunk is allocated; when
+// that would pass the limit or fails, chunks with no block in use are
+// released first. With no request running every chunk is empty, so a
+// request within the budget then always gets its block (device permitting).
+class DeviceArena {
+   public:
+    static constexpr size_t kGranule = (size_t)2 << 20;
+    static constexpr size_t kChunk = (size_t)4 << 30;
+    explicit DeviceArena(size_t limit) : limit_(limit) {}
+    ~DeviceArena() {
+        for (auto &c : chunks_) (void)hipFree(c.base);
+    }
+    // a block of at least bytes (rounded up to the granule); false if the
+    // budget or the device cannot provide it now
+    bool get(size_t bytes, void **p, size_t *got) {
+        const size_t need = (bytes + kGranule - 1) / kGranule * kGranule;
+        bool ok = take(need, p) || (grow(need) && take(need, p));
+        if (!ok) {
+            release_empty();
+            ok = grow(need) && take(need, p);
+        }
+        if (ok) *got = need;
+        return ok;
+    }
+    void put(void *p, size_t bytes) {
+        char *q = static_cast<char *>(p);
+        for (auto &c : chunks_) {
+            if (q < c.base || q >= c.base + c.size) continue;
+            size_t off = (size_t)(q - c.base), len = bytes;
+            auto next = c.free.lower_bound(off);
+            if (next != c.free.end() && off + len == next->first) {   // merge with the next range
+                len += next->second;
+                next = c.free.erase(next);
+            }
+            if (next != c.free.begin()) {                             // and with the previous one
+                auto prev = std::prev(next);
+                if (prev->first + prev->second == off) {
+                    prev->second += len;
+                    return;
+                }
+            }
+            c.free.emplace(off, len);
+            return;
+        }
+    }
+    size_t bytes_held() const {
+        size_t t = 0;
+        for (const auto &c : chunks_) t += c.size;
+        return t;
+    }
+
+   private:
+    struct Chunk {
+        char *base;
+        size_t size;
+        std::map<size_t, size_t> free;   // offset -> length
+    };
+    bool take(size_t need, void **p) {
+        Chunk *bc = nullptr;
+        std::map<size_t, size_t>::iterator best;
+        for (auto &c : chunks_)
+            for (auto it = c.free.begin(); it != c.free.end(); ++it)
+                if (it->second >= need && (!bc || it->second < best->second)) {
+                    bc = &c;
+                    best = it;
+                }
+        if (!bc) return false;
+        const size_t off = best->first, len = best->second;
+        bc->free.erase(best);
+        if (len > need) bc->free.emplace(off + need, len - need);
+        *p = bc->base + off;
+        return true;
+    }
+    bool grow(size_t need) {
+        size_t size = std::max(need, std::min(kChunk, limit_));
+        if (bytes_held() + size > limit_) size = need;
+        if (bytes_held() + size > limit_) return false;
+        void *b = nullptr;
+        if (hipMalloc(&b, size) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        Chunk c{static_cast<char *>(b), size, {}};
+        c.free.emplace(0, size);
+        chunks_.push_back(std::move(c));
+        return true;
+    }
+    void release_empty() {
+        for (size_t k = 0; k < chunks_.size();) {
+            Chunk &c = chunks_[k];
+            if (c.free.size() == 1 && c.free.begin()->first == 0 && c.free.begin()->second == c.size) {
+                (void)hipFree(c.base);
+                chunks_.erase(chunks_.begin() + k);
+            } else {
+                ++k;
+            }
+        }
+    }
+    size_t limit_;
+    std::vector<Chunk> chunks_;
+};
+
 // ------------------------------------------------------------ GPU executor
-// Device workspaces, pinned host blocks and events of finished requests are
-// kept for reuse: hipFree synchronises the whole device, which would stall
-// every other stream at each completion. A request takes the smallest cached
-// block that fits and is at most 1.25 times its size; the device cache is
-// trimmed (freed) when a new allocation fails or when it would exceed cap
-// bytes (half the memory budget).
+// Device workspaces come from the arena above; pinned host blocks and events
+// of finished requests are kept for reuse (a request takes the smallest
+// cached host block that fits and is at most 1.25 times its size).
 class GpuExecutor : public Executor {
    public:
-    GpuExecutor(int dev, int nstreams, size_t cap) : dev_(dev), cap_(cap) {
+    GpuExecutor(int dev, int nstreams, size_t budget) : dev_(dev), arena_(budget) {
         (void)hipSetDevice(dev_);
         for (int k = 0; k < nstreams; ++k) {
             hipStream_t s;
@@ -109,27 +217,27 @@ class GpuExecutor : public Executor {
     ~GpuExecutor() override {
         (void)hipSetDevice(dev_);
         for (auto s : streams_) (void)hipStreamDestroy(s);
-        trim_device();
         for (auto &kv : host_cache_) (void)hipHostFree(kv.second);
         for (auto e : events_) (void)hipEventDestroy(e);
     }
     bool ok() const { return !streams_.empty(); }
     size_t footprint(const Req &r) override {
-        return round_up(make_plan(r.p.n, r.p.d, r.p.m, r.prec, true, true).total, kGranule);
+        return round_up(make_plan(r.p.n, r.p.d, r.p.m, r.prec, true, true).total,
+                        DeviceArena::kGranule);
     }
     size_t held(const Req &r) override { return r.ws_bytes; }
     bool start(Req &r) override {
         (void)hipSetDevice(dev_);
         const Plan P = make_plan(r.p.n, r.p.d, r.p.m, r.prec, true, true);
         const size_t nn = (size_t)r.p.n * r.p.n, dbytes = (size_t)r.p.n * r.p.m;
-        if (alloc_fails() || !get_device(P.total, &r.ws, &r.ws_bytes)) {
+        if (alloc_fails() || !arena_.get(P.total, &r.ws, &r.ws_bytes)) {
             r.ws = nullptr;
             r.status = BN_ENOMEM;
             return false;
         }
         // pinned host block: post (n*n), diag (16), data (n*m)
         if (!get_host((nn + 16) * 8 + dbytes + 8, &r.hpin, &r.hpin_bytes)) {
-            put_device(r.ws, r.ws_bytes);
+            arena_.put(r.ws, r.ws_bytes);
             r.ws = nullptr;
             r.status = BN_ENOMEM;
             return false;
@@ -188,13 +296,12 @@ class GpuExecutor : public Executor {
         if (r.ev0) events_.push_back(r.ev0);
         if (r.ev1) events_.push_back(r.ev1);
         if (r.hpin) host_cache_.emplace(r.hpin_bytes, r.hpin);
-        if (r.ws) put_device(r.ws, r.ws_bytes);
+        if (r.ws) arena_.put(r.ws, r.ws_bytes);
         r.ev0 = r.ev1 = nullptr;
         r.hpin = r.ws = nullptr;
     }
 
    private:
-    static constexpr size_t kGranule = (size_t)2 << 20;   // device blocks: multiples of 2 MiB
     static size_t round_up(size_t x, size_t g) { return (x + g - 1) / g * g; }
     static bool take(std::multimap<size_t, void *> &c, size_t need, void **p, size_t *got) {
         auto it = c.lower_bound(need);
@@ -203,37 +310,6 @@ class GpuExecutor : public Executor {
         *got = it->first;
         c.erase(it);
         return true;
-    }
-    bool get_device(size_t bytes, void **p, size_t *got) {
-        const size_t need = round_up(bytes, kGranule);
-        if (take(dev_cache_, need, p, got)) {
-            dev_cached_ -= *got;
-            return true;
-        }
-        if (hipMalloc(p, need) != hipSuccess) {
-            (void)hipGetLastError();
-            trim_device();
-            if (hipMalloc(p, need) != hipSuccess) {
-                (void)hipGetLastError();
-                return false;
-            }
-        }
-        *got = need;
-        return true;
-    }
-    void put_device(void *p, size_t bytes) {
-        if (dev_cached_ + bytes > cap_) trim_device();
-        if (bytes > cap_) {
-            (void)hipFree(p);
-            return;
-        }
-        dev_cache_.emplace(bytes, p);
-        dev_cached_ += bytes;
-    }
-    void trim_device() {
-        for (auto &kv : dev_cache_) (void)hipFree(kv.second);
-        dev_cache_.clear();
-        dev_cached_ = 0;
     }
     bool get_host(size_t bytes, void **p, size_t *got) {
         const size_t need = round_up(bytes, (size_t)64 << 10);
@@ -257,11 +333,10 @@ class GpuExecutor : public Executor {
     }
 
     int dev_;
-    size_t cap_;
     std::vector<hipStream_t> streams_;
     size_t next_ = 0;
-    std::multimap<size_t, void *> dev_cache_, host_cache_;
-    size_t dev_cached_ = 0;
+    DeviceArena arena_;
+    std::multimap<size_t, void *> host_cache_;
     std::vector<hipEvent_t> events_;
 };
 
@@ -498,7 +573,7 @@ bn_status bn_server_create(size_t mem_budget_bytes, int32_t max_active, void **s
             if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return BN_EDEVICE;
             budget = free_b / 10 * 9;
         }
-        auto *g = new bnk::GpuExecutor(dev, std::min(max_active, 8), budget / 2);
+        auto *g = new bnk::GpuExecutor(dev, std::min(max_active, 8), budget);
         if (!g->ok()) {
             delete g;
             return BN_EDEVICE;
