@@ -2943,6 +2943,29 @@ static hipError_t launch_lattice_fused(const LatticeArgs &a, const PolX32::Store
                                        const PolX32::Store &R, hipStream_t st,
                                        PhaseEvents *ev);
 
+// Fork of a second stream off the solve's stream and its join: two events
+// (no timing), destroyed when the helper goes out of scope (HIP releases an
+// event recorded and waited on only after the waits are satisfied).
+struct SweepFork {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t open(hipStream_t st, hipStream_t side) {
+        hipError_t e = hipEventCreateWithFlags(&e0, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, e0, 0);
+        return e;
+    }
+    hipError_t join(hipStream_t st, hipStream_t side) {
+        hipError_t e = hipEventRecord(e1, side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, e1, 0);
+        return e;
+    }
+    ~SweepFork() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
 template <class P>
 hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
                           const typename P::Store &L, const typename P::Store &R,
@@ -3042,6 +3065,16 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     const int nh = n - a.bL;
     const size_t smL = align16(SliceLds<P>::bytes_per_entry * ((size_t)a.bL << (a.bL - 1))) +
                        sizeof(V) * ((size_t)1 << a.bL) + 2 * ((size_t)1 << a.bL);
+    // The backward sweep needs alpha but not L: with a.side set it runs on that
+    // stream, forked after alpha and joined before Gamma, so that its small
+    // layers overlap the forward sweep's.
+    SweepFork fork;
+    hipStream_t sb = st;
+    if (a.side && !a.fwd_only) {
+        const hipError_t e = fork.open(st, a.side);
+        if (e != hipSuccess) return e;
+        sb = a.side;
+    }
     for (int h = 0; h <= nh; ++h) {
         const unsigned nb = a.tiles_per_layer[h];
         hipLaunchKernelGGL(k_fwd<P>, dim3(nb), dim3(kThreads), smL, st, n, a.bL, h,
@@ -3059,9 +3092,13 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
     }
     for (int h = nh; h >= 0; --h) {
         const unsigned nb = a.tiles_per_layer[h];
-        hipLaunchKernelGGL(k_bwd<P>, dim3(nb), dim3(kThreads), smL, st, n, a.bL, h,
+        hipLaunchKernelGGL(k_bwd<P>, dim3(nb), dim3(kThreads), smL, sb, n, a.bL, h,
                            hord_offset(nh, h), tb, alpha, R, a.cnt);
         BN_CHECK_LAUNCH();
+    }
+    if (sb != st) {
+        const hipError_t e = fork.join(st, sb);
+        if (e != hipSuccess) return e;
     }
     rec(4);
     return launch_gamma_edges<P>(a, L, R, st, ev);

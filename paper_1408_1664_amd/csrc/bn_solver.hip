@@ -419,8 +419,35 @@ static LatticeArgs lattice_args(const Plan &P, char *ws, double *dev_post, doubl
     return a;
 }
 
-static bn_status run_lattice(const Plan &P, char *ws, const LatticeArgs &a, hipStream_t st,
+// The backward sweep of a large lattice runs on a second stream of the
+// device (one per device, created on first use, default priority), forked
+// after alpha and joined before Gamma, so that the small layers of the two
+// sweeps overlap. From n = 24 (smaller lattices are dispatch-bound and are
+// served many at a time on streams of their own); BN_SWEEP_FORK=0 keeps
+// both sweeps on the caller's stream. Solves that run at the same time on
+// one device share that second stream (their backward sweeps then queue
+// behind each other).
+constexpr int kSweepForkFromN = 24;
+static std::mutex g_side_mu;
+static hipStream_t g_side[64] = {};
+static hipStream_t side_stream(const Plan &P) {
+    if (P.n < kSweepForkFromN || P.fused) return nullptr;
+    static const bool on = [] {
+        const char *e = getenv("BN_SWEEP_FORK");
+        return !(e && e[0] == '0');
+    }();
+    if (!on) return nullptr;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    if (!g_side[dev] && hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking) != hipSuccess)
+        g_side[dev] = nullptr;
+    return g_side[dev];
+}
+
+static bn_status run_lattice(const Plan &P, char *ws, LatticeArgs a, hipStream_t st,
                              PhaseEvents *ev) {
+    a.side = side_stream(P);
     hipError_t e;
     if (P.x32) {
         PolX32::Store al{reinterpret_cast<float *>(ws + P.o_alpha_f),
@@ -561,6 +588,16 @@ bn_status edge_posteriors_host(const bn_problem *p, bn_precision prec, double *p
                     (unsigned long long)rep->saturated, (unsigned long long)rep->flushed,
                     (unsigned long long)rep->fallback_tiles, rep->ms_scores, rep->ms_alpha,
                     rep->ms_fwd, rep->ms_bwd, rep->ms_gamma, rep->ms_edges, rep->ms_total);
+        if (log_level() >= 2 && P.bG == 12) {
+            // list heads: Gamma endpoints given a second scale, Gamma items and
+            // alpha tiles (or, fused, blocks) recomputed in the number system
+            uint32_t cnt[3] = {0, 0, 0};
+            (void)hipMemcpy(&cnt[0], ws + P.o_rtG, 4, hipMemcpyDeviceToHost);
+            (void)hipMemcpy(&cnt[1], ws + P.o_fbG, 4, hipMemcpyDeviceToHost);
+            if (P.o_fbA) (void)hipMemcpy(&cnt[2], ws + P.o_fbA, 4, hipMemcpyDeviceToHost);
+            fprintf(stderr, "[bn] lists gamma_second_scale=%u gamma_fallback=%u alpha_fallback=%u\n",
+                    cnt[0], cnt[1], cnt[2]);
+        }
     }
     if (timing)
         for (int k = 0; k < 7; ++k) (void)hipEventDestroy(ev.ev[k]);

@@ -93,6 +93,21 @@ def test_local_scores_k2_mixed_arity():
         np.testing.assert_allclose(got[i], ref[i, expand(masks, i)], rtol=1e-12, atol=1e-10)
 
 
+@pytest.mark.parametrize("kind", ["bdeu", "k2"])
+def test_local_scores_large_histograms(kind):
+    """Families with more than 2048 histogram bins (here up to 5 * 5*5*4*4*4
+    = 8000 at d = 5) take the one-family-per-workgroup score kernel; smaller
+    ones are counted four families per workgroup, one wave each (the tests
+    above)."""
+    ar = [5, 4, 5, 4, 3, 3, 2, 4, 5]
+    ds = datagen.random_dag_dataset(9, 400, ar, 3, 0.8, seed=23)
+    got = bn.local_scores(ds.data, ds.arity, 5, score=kind, ess=1.5)
+    ref = O.local_scores(ds.data, ds.arity, 5, O.K2 if kind == "k2" else O.BDEU, 1.5)
+    masks = ranked_masks(8, 5)
+    for i in range(9):
+        np.testing.assert_allclose(got[i], ref[i, expand(masks, i)], rtol=1e-12, atol=1e-10)
+
+
 # ------------------------------------------------------- whole path, a1-a7
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
