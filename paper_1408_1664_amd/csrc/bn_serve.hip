@@ -40,6 +40,7 @@
 #include <vector>
 
 #include "../../include/bn.h"
+#include "bn_arena.h"
 #include "bn_solver.h"
 
 namespace bnk {
@@ -91,114 +92,16 @@ class Executor {
 };
 
 // ------------------------------------------------------------ device arena
-// Workspaces of the requests come from chunks of device memory that the
-// server allocates rarely and keeps: hipMalloc per request costs more than a
-// small solve (and serialises the worker), hipFree synchronises the whole
-// device. A chunk is kChunk bytes (or the request's size when larger),
-// and the chunks together stay within the memory budget (limit); their free
-// ranges (offset -> length, multiples of the 2 MiB granule) are kept
-// coalesced, and a request takes the smallest free range that fits (best
-// fit over every chunk). When no range fits, a new chunk is allocated; when
-// that would pass the limit or fails, chunks with no block in use are
-// released first. With no request running every chunk is empty, so a
-// request within the budget then always gets its block (device permitting).
-class DeviceArena {
-   public:
-    static constexpr size_t kGranule = (size_t)2 << 20;
-    static constexpr size_t kChunk = (size_t)4 << 30;
-    explicit DeviceArena(size_t limit) : limit_(limit) {}
-    ~DeviceArena() {
-        for (auto &c : chunks_) (void)hipFree(c.base);
+// Workspaces come from the chunked arena of bn_arena.h over device memory.
+struct HipMem {
+    static bool alloc(size_t bytes, void **p) {
+        if (hipMalloc(p, bytes) == hipSuccess) return true;
+        (void)hipGetLastError();
+        return false;
     }
-    // a block of at least bytes (rounded up to the granule); false if the
-    // budget or the device cannot provide it now
-    bool get(size_t bytes, void **p, size_t *got) {
-        const size_t need = (bytes + kGranule - 1) / kGranule * kGranule;
-        bool ok = take(need, p) || (grow(need) && take(need, p));
-        if (!ok) {
-            release_empty();
-            ok = grow(need) && take(need, p);
-        }
-        if (ok) *got = need;
-        return ok;
-    }
-    void put(void *p, size_t bytes) {
-        char *q = static_cast<char *>(p);
-        for (auto &c : chunks_) {
-            if (q < c.base || q >= c.base + c.size) continue;
-            size_t off = (size_t)(q - c.base), len = bytes;
-            auto next = c.free.lower_bound(off);
-            if (next != c.free.end() && off + len == next->first) {   // merge with the next range
-                len += next->second;
-                next = c.free.erase(next);
-            }
-            if (next != c.free.begin()) {                             // and with the previous one
-                auto prev = std::prev(next);
-                if (prev->first + prev->second == off) {
-                    prev->second += len;
-                    return;
-                }
-            }
-            c.free.emplace(off, len);
-            return;
-        }
-    }
-    size_t bytes_held() const {
-        size_t t = 0;
-        for (const auto &c : chunks_) t += c.size;
-        return t;
-    }
-
-   private:
-    struct Chunk {
-        char *base;
-        size_t size;
-        std::map<size_t, size_t> free;   // offset -> length
-    };
-    bool take(size_t need, void **p) {
-        Chunk *bc = nullptr;
-        std::map<size_t, size_t>::iterator best;
-        for (auto &c : chunks_)
-            for (auto it = c.free.begin(); it != c.free.end(); ++it)
-                if (it->second >= need && (!bc || it->second < best->second)) {
-                    bc = &c;
-                    best = it;
-                }
-        if (!bc) return false;
-        const size_t off = best->first, len = best->second;
-        bc->free.erase(best);
-        if (len > need) bc->free.emplace(off + need, len - need);
-        *p = bc->base + off;
-        return true;
-    }
-    bool grow(size_t need) {
-        size_t size = std::max(need, std::min(kChunk, limit_));
-        if (bytes_held() + size > limit_) size = need;
-        if (bytes_held() + size > limit_) return false;
-        void *b = nullptr;
-        if (hipMalloc(&b, size) != hipSuccess) {
-            (void)hipGetLastError();
-            return false;
-        }
-        Chunk c{static_cast<char *>(b), size, {}};
-        c.free.emplace(0, size);
-        chunks_.push_back(std::move(c));
-        return true;
-    }
-    void release_empty() {
-        for (size_t k = 0; k < chunks_.size();) {
-            Chunk &c = chunks_[k];
-            if (c.free.size() == 1 && c.free.begin()->first == 0 && c.free.begin()->second == c.size) {
-                (void)hipFree(c.base);
-                chunks_.erase(chunks_.begin() + k);
-            } else {
-                ++k;
-            }
-        }
-    }
-    size_t limit_;
-    std::vector<Chunk> chunks_;
+    static void release(void *p) { (void)hipFree(p); }
 };
+using DeviceArena = Arena<HipMem>;
 
 // ------------------------------------------------------------ GPU executor
 // Device workspaces come from the arena above; pinned host blocks and events
