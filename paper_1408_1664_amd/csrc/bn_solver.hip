@@ -285,8 +285,9 @@ static Plan plan_of(int n, int d_in, int m, bn_precision prec, bool with_data, b
 // faster (n = 30: 103.7 against 120.4 ms; n = 25: 5.6 against 6.9 ms), so
 // the fused sweeps are taken only where alpha would not fit: from n = 23
 // when the materialised workspace exceeds kFuseAboveBytes (a device of
-// 288 GB, less room for the caller's own buffers). BN_FUSED_ALPHA=1 takes
-// the fused path from n = 10, =0 never (tests, measurements).
+// 288 GB, less room for the caller's own buffers) and the fused one is
+// smaller. BN_FUSED_ALPHA=1 takes the fused path from n = 10, =0 never
+// (tests, measurements).
 static constexpr size_t kFuseAboveBytes = 240ull << 30;
 
 Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool with_post) {
@@ -295,8 +296,12 @@ Plan make_plan(int n, int d_in, int m, bn_precision prec, bool with_data, bool w
         if (!strcmp(fa, "1")) return plan_of(n, d_in, m, prec, with_data, with_post, 1);
     }
     Plan P = plan_of(n, d_in, m, prec, with_data, with_post, 0);
-    if (n >= 23 && P.x32 && P.lin_mode != 0 && P.total > kFuseAboveBytes)
-        P = plan_of(n, d_in, m, prec, with_data, with_post, 1);
+    if (n >= 23 && P.x32 && P.lin_mode != 0 && P.total > kFuseAboveBytes) {
+        // the block seeds, K(9, d - 1) of 8 bytes per 512 entries, outgrow
+        // alpha's 5 bytes per entry from d = 6: keep the smaller plan
+        Plan F = plan_of(n, d_in, m, prec, with_data, with_post, 1);
+        if (F.total < P.total) P = F;
+    }
     return P;
 }
 

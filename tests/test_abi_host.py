@@ -81,6 +81,16 @@ def test_workspace_grows_with_n_and_precision(monkeypatch):
     monkeypatch.setenv("BN_FUSED_ALPHA", "1")
     assert bn.workspace_bytes(31, 3, 500, "fp32") < 100e9
     monkeypatch.delenv("BN_FUSED_ALPHA")
+    # the plan fuses by itself only where materialised alpha passes 240 GiB
+    # and the fused plan is smaller: n = 31, d = 4 (253.6 -> 161.5 GiB); at
+    # n = 30, d = 6 the 9-bit block seeds outgrow alpha, so alpha stays
+    monkeypatch.setenv("BN_FUSED_ALPHA", "0")
+    m31, m30 = bn.workspace_bytes(31, 4, 500, "fp32"), bn.workspace_bytes(30, 6, 500, "fp32")
+    monkeypatch.setenv("BN_FUSED_ALPHA", "1")
+    f31, f30 = bn.workspace_bytes(31, 4, 500, "fp32"), bn.workspace_bytes(30, 6, 500, "fp32")
+    monkeypatch.delenv("BN_FUSED_ALPHA")
+    assert m31 > 240 * 2 ** 30 > f31 and bn.workspace_bytes(31, 4, 500, "fp32") == f31
+    assert f30 > m30 and bn.workspace_bytes(30, 6, 500, "fp32") == m30
     with pytest.raises(bn.BnError):
         bn.workspace_bytes(1, 2, 10, "fp32")
     with pytest.raises(bn.BnError):

@@ -106,6 +106,29 @@ def test_no_data_closed_form_at_large_n(n, prec, fused, monkeypatch):
     assert diag[1] < (1e-9 if prec == "fp64" else 1e-4)
 
 
+def test_n31_d4_plan_fuses_by_itself(monkeypatch):
+    """n = 31, d = 4: materialised alpha would take 253.6 GiB, so the plan
+    takes the fused sweeps (161.5 GiB) without being asked; m = 0 has the
+    closed form."""
+    n, d = 31, 4
+    monkeypatch.setenv("BN_FUSED_ALPHA", "1")
+    fused_bytes = bn.workspace_bytes(n, d, 0, "fp32")
+    monkeypatch.delenv("BN_FUSED_ALPHA")
+    assert bn.workspace_bytes(n, d, 0, "fp32") == fused_bytes
+    if not _fits(n, d, 0, "fp32"):
+        pytest.skip("the n=31, d=4 workspace does not fit in free device memory")
+    rho = [Fraction(1, math.comb(n - 1, k)) for k in range(d + 1)]
+    want = float(m0_closed_form(n, d, rho))
+    print("m=0 n=31 d=4 fp32, plan's own choice (fused)", flush=True)
+    P, diag = _solve_dev(np.zeros((n, 0), np.uint8), np.full(n, 2, np.uint8), d, "fp32")
+    off = P[~np.eye(n, dtype=bool)]
+    err = np.abs(off - want).max()
+    print(f"m=0 n=31 d=4: closed form {want:.12f}, max |dP| = {err:.3e}, "
+          f"residual {diag[1]:.2e}", flush=True)
+    assert err <= 1e-5
+    assert diag[1] < 1e-4
+
+
 @pytest.mark.parametrize("fused", ["0", "1"])
 def test_n31_fp32_properties(fused, monkeypatch):
     n, m, d = 31, 500, 3
