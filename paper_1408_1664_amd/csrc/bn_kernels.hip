@@ -262,12 +262,17 @@ __global__ void k_scores(int n, int m, const uint8_t *__restrict__ data,
 // histograms of at most kScoreWaveBins bins (every family of the problem):
 // a quarter of the workgroups and no workgroup barriers. Parents, counts and
 // the wave's sum stay within the wave (LDS accesses of one wave run in
-// order; the wave barriers keep the compiler from moving them).
+// order; the wave barriers keep the compiler from moving them). Each lane
+// takes four samples per step, with every load of the step issued before
+// the counts. When every variable has the same arity (lgt non-null, d <= 4),
+// the log-gamma values come from the tables of k_lgamma_table: a family with
+// k parents has q = r^k configurations, so its hyperparameters depend on k
+// alone; the table entries are the same lgamma values, so the sums are too.
 constexpr int kScoreWaveBins = 2048;
 __global__ void __launch_bounds__(kThreads)
 k_scores_w(int n, int m, const uint8_t *__restrict__ data, const uint8_t *__restrict__ arity,
            uint32_t K, int kind, double ess, const uint32_t *__restrict__ famask, int max_bins,
-           double *__restrict__ out) {
+           const double *__restrict__ lgt, double *__restrict__ out) {
     extern __shared__ int hist_all[];
     __shared__ int par_all[4][32];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -294,37 +299,77 @@ k_scores_w(int n, int m, const uint8_t *__restrict__ data, const uint8_t *__rest
     for (int b = l; b < bins; b += 64) hist[b] = 0;
     __builtin_amdgcn_wave_barrier();
     const uint8_t *xi = data + (size_t)i * m;
-    for (int s = l; s < m; s += 64) {
-        int key = 0;
+    constexpr int U = 4;
+    for (int s0 = l; s0 < m; s0 += 64 * U) {
+        int key[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) key[u] = 0;
         for (int p = 0; p < np; ++p) {
             const int var = par[p];
-            key = key * arity[var] + data[(size_t)var * m + s];
+            const int ar = arity[var];
+            const uint8_t *row = data + (size_t)var * m;
+            int x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int s = s0 + 64 * u;
+                x[u] = s < m ? row[s] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) key[u] = key[u] * ar + x[u];
         }
-        const int bin = key * ri + xi[s];
-        if (bin < bins) atomicAdd(&hist[bin], 1);  // values >= arity are ignored
+        int xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int s = s0 + 64 * u;
+            xv[u] = s < m ? (int)xi[s] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int bin = key[u] * ri + xv[u];
+            // samples past the end count nowhere; values >= arity are ignored
+            if (s0 + 64 * u < m && bin < bins) atomicAdd(&hist[bin], 1);
+        }
     }
     __builtin_amdgcn_wave_barrier();
-    double a_j, a_jk;
-    if (kind == 0) {
-        a_j = ess / q;
-        a_jk = ess / ((double)q * ri);
-    } else {
-        a_j = ri;
-        a_jk = 1.0;
-    }
-    const double lg_aj = lgamma(a_j), lg_ajk = lgamma(a_jk);
     double acc = 0.0;
-    for (int j = l; j < q; j += 64) {
-        int nj = 0;
-        double sj = 0.0;
-        for (int k = 0; k < ri; ++k) {
-            const int c = hist[j * ri + k];
-            if (c) {
-                sj += lgamma(a_jk + c) - lg_ajk;
-                nj += c;
+    if (lgt) {
+        const int m1 = m + 1;
+        const double *lj = lgt + (size_t)(2 * np) * m1, *ljk = lj + m1;
+        const double lg_aj = lj[0], lg_ajk = ljk[0];
+        for (int j = l; j < q; j += 64) {
+            int nj = 0;
+            double sj = 0.0;
+            for (int k = 0; k < ri; ++k) {
+                const int c = hist[j * ri + k];
+                if (c) {
+                    sj += ljk[c] - lg_ajk;
+                    nj += c;
+                }
             }
+            if (nj) acc += sj + lg_aj - lj[nj];
         }
-        if (nj) acc += sj + lg_aj - lgamma(a_j + nj);
+    } else {
+        double a_j, a_jk;
+        if (kind == 0) {
+            a_j = ess / q;
+            a_jk = ess / ((double)q * ri);
+        } else {
+            a_j = ri;
+            a_jk = 1.0;
+        }
+        const double lg_aj = lgamma(a_j), lg_ajk = lgamma(a_jk);
+        for (int j = l; j < q; j += 64) {
+            int nj = 0;
+            double sj = 0.0;
+            for (int k = 0; k < ri; ++k) {
+                const int c = hist[j * ri + k];
+                if (c) {
+                    sj += lgamma(a_jk + c) - lg_ajk;
+                    nj += c;
+                }
+            }
+            if (nj) acc += sj + lg_aj - lgamma(a_j + nj);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (l == 0) out[fam] = acc;
@@ -2765,16 +2810,19 @@ __device__ inline void count_cells2(const uint32_t *__restrict__ bits, int W, in
         for (int sft = 8; sft > 0; sft >>= 1) cnt[c] += __shfl_xor(cnt[c], sft, 16);
 }
 
-// Log-gamma tables of the binary score path: for k = 0..4 parents,
+// Log-gamma tables of the score paths for data whose variables all have
+// arity r: for k = 0..4 parents (q = r^k configurations),
 // lgt[(2k) * (m+1) + c] = lgamma(a_j + c) and lgt[(2k+1) * (m+1) + c] =
-// lgamma(a_jk + c), c = 0..m, with the hyperparameters of family_score2.
-__global__ void k_lgamma_table(int m, int kind, double ess, double *__restrict__ lgt) {
+// lgamma(a_jk + c), c = 0..m, with the BDeu (a_j = ess / q, a_jk =
+// ess / (q r)) or K2 (a_j = r, a_jk = 1) hyperparameters.
+__global__ void k_lgamma_table(int m, int r, int kind, double ess, double *__restrict__ lgt) {
     const int m1 = m + 1;
     for (int x = blockIdx.x * kThreads + threadIdx.x; x < 10 * m1; x += gridDim.x * kThreads) {
         const int row = x / m1, c = x - row * m1, k = row >> 1;
-        const double q = (double)(1 << k);
-        const double a = (row & 1) ? (kind == 0 ? ess / (2.0 * q) : 1.0)
-                                   : (kind == 0 ? ess / q : 2.0);
+        int qi = 1;
+        for (int j = 0; j < k; ++j) qi *= r;
+        const double a = (row & 1) ? (kind == 0 ? ess / ((double)qi * r) : 1.0)
+                                   : (kind == 0 ? ess / qi : (double)r);
         lgt[x] = lgamma(a + c);
     }
 }
@@ -2897,27 +2945,34 @@ uint32_t hord_offset(int nh, int h) {
 
 hipError_t launch_scores(int n, int m, const uint8_t *data, const uint8_t *arity, uint32_t K,
                          int kind, double ess, const uint32_t *famask, int max_bins,
-                         double *out, hipStream_t st, uint32_t *bits) {
+                         double *out, hipStream_t st, uint32_t *bits, int uniform_r,
+                         double *lgt) {
+    const dim3 tgrid((unsigned)std::min((10 * (m + 1) + kThreads - 1) / kThreads, 1024));
     if (bits) {
         // all-binary data, d <= 4: counts from bit planes
         const int W = (m + 31) / 32;
         hipLaunchKernelGGL(k_pack2, dim3((unsigned)((n * W + kThreads - 1) / kThreads)),
                            dim3(kThreads), 0, st, n, m, W, data, bits);
         BN_CHECK_LAUNCH();
-        double *lgt = reinterpret_cast<double *>(bits + (size_t)2 * n * W);
-        hipLaunchKernelGGL(k_lgamma_table, dim3((unsigned)std::min((10 * (m + 1) + kThreads - 1) / kThreads, 1024)),
-                           dim3(kThreads), 0, st, m, kind, ess, lgt);
+        hipLaunchKernelGGL(k_lgamma_table, tgrid, dim3(kThreads), 0, st, m, 2, kind, ess, lgt);
         BN_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_scores2, dim3((unsigned)((n * K + 15) / 16)), dim3(kThreads), 0, st,
                            n, W, m, K, famask, (const uint32_t *)bits, (const double *)lgt, out);
         BN_CHECK_LAUNCH();
         return hipSuccess;
     }
-    if (max_bins <= kScoreWaveBins)
+    if (max_bins <= kScoreWaveBins) {
+        const double *tab = nullptr;
+        if (uniform_r > 0) {
+            hipLaunchKernelGGL(k_lgamma_table, tgrid, dim3(kThreads), 0, st, m, uniform_r, kind,
+                               ess, lgt);
+            BN_CHECK_LAUNCH();
+            tab = lgt;
+        }
         hipLaunchKernelGGL(k_scores_w, dim3((unsigned)((n * (uint64_t)K + 3) / 4)), dim3(kThreads),
                            (size_t)4 * max_bins * sizeof(int), st, n, m, data, arity, K, kind, ess,
-                           famask, max_bins, out);
-    else
+                           famask, max_bins, tab, out);
+    } else
         hipLaunchKernelGGL(k_scores, dim3((unsigned)(n * K)), dim3(kThreads),
                            (size_t)max_bins * sizeof(int), st, n, m, data, arity, K, kind, ess,
                            famask, out);

@@ -360,15 +360,21 @@ static bn_status enqueue_scores(const Plan &P, const bn_problem *p, const uint8_
     Tables tb = tables_of(P, ws);
     HIPCHK(launch_setup(tb, P.bL, P.W, P.bG, P.bA, P.d, P.N, P.K, st));
     const int kind = p->score == BN_SCORE_K2 ? 1 : 0;
-    // all-binary data with d <= 4: the bit-plane counting path
-    bool binary = P.m > 0 && P.d <= 4;
-    for (int i = 0; i < P.n && binary; ++i) binary = p->arity[i] == 2;
+    // all-binary data with d <= 4: the bit-plane counting path; one arity r
+    // for every variable and d <= 4: log-gamma tables (q = r^k)
+    bool uniform = P.d <= 4;
+    for (int i = 1; i < P.n && uniform; ++i) uniform = p->arity[i] == p->arity[0];
+    bool binary = P.m > 0 && uniform && p->arity[0] == 2;
     if (const char *e = getenv("BN_SCORE_BITS"))
         if (e[0] == '0') binary = false;
+    if (const char *e = getenv("BN_SCORE_TABLES"))
+        if (e[0] == '0') uniform = false;
+    uint32_t *bits = reinterpret_cast<uint32_t *>(ws + P.o_bits);
+    double *lgt = reinterpret_cast<double *>(bits + (size_t)2 * P.n * ((std::max(P.m, 1) + 31) / 32));
     HIPCHK(launch_scores(P.n, P.m, dev_data, reinterpret_cast<const uint8_t *>(ws + P.o_arity), P.K,
                          kind, p->ess, tb.famask, max_bins_of(p, P.d),
-                         reinterpret_cast<double *>(ws + P.o_logp), st,
-                         binary ? reinterpret_cast<uint32_t *>(ws + P.o_bits) : nullptr));
+                         reinterpret_cast<double *>(ws + P.o_logp), st, binary ? bits : nullptr,
+                         uniform ? p->arity[0] : 0, lgt));
     return BN_OK;
 }
 

@@ -84,6 +84,25 @@ def test_local_scores_binary_bitplanes(kind):
         np.testing.assert_allclose(got[i], ref[i, expand(masks, i)], rtol=1e-12, atol=1e-10)
 
 
+@pytest.mark.parametrize("kind", ["bdeu", "k2"])
+@pytest.mark.parametrize("r,d,m", [(3, 3, 1001), (3, 4, 70), (4, 2, 257), (5, 4, 300)])
+def test_local_scores_uniform_arity_tables(kind, r, d, m, monkeypatch):
+    """Every variable of arity r, d <= 4: the log-gamma values come from
+    tables (q = r^k for k parents). Against the oracle, and bitwise against
+    the same kernel with lgamma evaluated per family (BN_SCORE_TABLES=0);
+    m = 70 and 257 leave the four-sample steps ragged."""
+    ds = datagen.random_dag_dataset(10, m, r, min(d, 3), 1.0, seed=31 + r + d)
+    print(f"uniform arity scores r={r} d={d} m={m} kind={kind}", flush=True)
+    got = bn.local_scores(ds.data, ds.arity, d, score=kind, ess=1.5)
+    ref = O.local_scores(ds.data, ds.arity, d, O.K2 if kind == "k2" else O.BDEU, 1.5)
+    masks = ranked_masks(9, d)
+    for i in range(10):
+        np.testing.assert_allclose(got[i], ref[i, expand(masks, i)], rtol=1e-12, atol=1e-10)
+    monkeypatch.setenv("BN_SCORE_TABLES", "0")
+    per_family = bn.local_scores(ds.data, ds.arity, d, score=kind, ess=1.5)
+    assert np.array_equal(got, per_family)
+
+
 def test_local_scores_k2_mixed_arity():
     ds = datagen.random_dag_dataset(9, 333, [2, 3, 4, 2, 5, 3, 2, 2, 3], 3, 0.7, seed=8)
     got = bn.local_scores(ds.data, ds.arity, 3, score="k2")
