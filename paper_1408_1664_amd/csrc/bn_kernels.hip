@@ -1822,9 +1822,9 @@ __device__ inline void lin_zeta_down(double *g, int q) {
 //      needed and bits 0..7 are final by then, so threads whose pattern has
 //      more than d ones skip C (whole waves for small d).
 // The kernel below wraps this body with its register cap.
-template <class P>
+template <class P, bool kSplit>
 __device__ __forceinline__ void
-gamma_tile_lin_body(int n, int d, int force_fb, GammaGeom gg, Tables tb,
+gamma_tile_lin_body(int n, int d, int force_fb, int vsplit, GammaGeom gg, Tables tb,
                     typename P::Store L, typename P::Store R, const typename P::V *__restrict__ qt,
                     typename P::V *__restrict__ Y1, typename P::V *__restrict__ part,
                     uint32_t *fb, uint32_t *rt) {
@@ -1845,20 +1845,32 @@ gamma_tile_lin_body(int n, int d, int force_fb, GammaGeom gg, Tables tb,
     const int t = threadIdx.x;
     const int hbits = n - bT;
     const uint32_t nblk = 1u << hbits;
-    uint32_t H = blockIdx.x;
-    if (nblk >= 64) H = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
+    // vsplit workgroups share a tile, workgroup v0 taking the endpoints
+    // v = v0 (mod vsplit); the first of them also writes the tile's partials
+    const int vs = kSplit ? vsplit : 1;
+    const uint32_t blk = kSplit ? blockIdx.x / (uint32_t)vs : blockIdx.x;
+    const int v0 = kSplit ? (int)(blockIdx.x % (uint32_t)vs) : 0;
+    uint32_t H = blk;
+    if (nblk >= 64) H = (blk & 7) * (nblk >> 3) + (blk >> 3);
     const uint64_t Hf = (uint64_t)H << bT;
     const uint64_t x0 = Hf | ((uint32_t)t << 4);   // the thread's first mask in layout A
     for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
     for (uint32_t x = t; x < gg.KT; x += kThreads) seedT[x] = tb.seedmask[x];
     if (t < n) sq[t] = qt[t];
-    if (t == 0) sfail = force_fb ? 1 : 0;
+    if (t == 0) sfail = force_fb && v0 == 0 ? 1 : 0;
     R16 Lw, Rown, Rv;                         // own L and Rp blocks; partners of the next endpoint
     const int hpc = __popcll(Hf);
+    // the workgroup's first endpoint, and the partner block it needs
+    int vfirst = v0;
+    while (vfirst < n && vfirst >= bT && ((Hf >> vfirst) & 1)) vfirst += vs;
     {
         Lw = P::load16_raw(L, x0);
         Rown = P::load16_raw(R, x0);
-        Rv = Rown;                            // endpoint 0 is a register bit
+        Rv = Rown;                            // a register bit needs no partner block
+        if (vfirst >= 4 && vfirst < bT)
+            Rv = P::load16_raw(R, Hf | ((uint32_t)(t | (1 << (vfirst - 4))) << 4));
+        else if (vfirst >= bT && vfirst < n)
+            Rv = P::load16_raw(R, x0 | (1ull << vfirst));
         __syncthreads();                      // sbin
         // invariant partials: sum of L(S) Rp(S) over the tile, per |x|; the
         // thread's entries have |x| = |t| + |r|
@@ -1885,7 +1897,7 @@ gamma_tile_lin_body(int n, int d, int force_fb, GammaGeom gg, Tables tb,
                 }
             }
             for (int w = 8; w > 0; w >>= 1) acc = P::add(acc, shfl_xor_v(acc, w));
-            if (l <= bT && j == 0) part[(size_t)H * (bT + 1) + l] = acc;
+            if (l <= bT && j == 0 && v0 == 0) part[(size_t)H * (bT + 1) + l] = acc;
         }
     }
     // scale of endpoint v: g_v at the top of the tile
@@ -1957,8 +1969,8 @@ gamma_tile_lin_body(int n, int d, int force_fb, GammaGeom gg, Tables tb,
             }
         }
         {   // partners of the next endpoint (none needed for register bits)
-            int vn = v + 1;
-            while (vn < n && vn >= bT && ((Hf >> vn) & 1)) ++vn;
+            int vn = v + vs;
+            while (vn < n && vn >= bT && ((Hf >> vn) & 1)) vn += vs;
             if (vn >= 4 && vn < bT) {
                 // tile bit vn: the block of thread t + 2^(vn-4) (own block if set)
                 Rv = P::load16_raw(R, Hf | ((uint32_t)(t | (1 << (vn - 4))) << 4));
@@ -2026,22 +2038,30 @@ gamma_tile_lin_body(int n, int d, int force_fb, GammaGeom gg, Tables tb,
     // the own Rp block is a partner only for the register bits 0..3: with a
     // loop of their own, it is dead in the loops over the other endpoints;
     // the tile bits and the bits above the tile get a loop each as well
-    for (int v = 0; v < 4 && v < n; ++v) endpoint(v);
-    for (int v = 4; v < bT && v < n; ++v) endpoint(v);
-    for (int v = bT; v < n; ++v) endpoint(v);
+    if constexpr (kSplit) {
+        int v = v0;
+        for (; v < 4 && v < n; v += vs) endpoint(v);
+        for (; v < bT && v < n; v += vs) endpoint(v);
+        for (; v < n; v += vs) endpoint(v);
+    } else {
+        for (int v = 0; v < 4 && v < n; ++v) endpoint(v);
+        for (int v = 4; v < bT && v < n; ++v) endpoint(v);
+        for (int v = bT; v < n; ++v) endpoint(v);
+    }
     if (t == 0 && sfail) fb_push(fb, H << 6);             // every endpoint
 }
 
 // Three waves per SIMD (168 registers, some spill), which measured faster
 // than two without spills: more waves hide the barrier and load latency of
 // the endpoint loops.
-template <class P>
+template <class P, bool kSplit>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
-k_gamma_tile_lin(int n, int d, int force_fb, GammaGeom gg, Tables tb, typename P::Store L,
+k_gamma_tile_lin(int n, int d, int force_fb, int vsplit, GammaGeom gg, Tables tb,
+                 typename P::Store L,
                  typename P::Store R, const typename P::V *__restrict__ qt,
                  typename P::V *__restrict__ Y1, typename P::V *__restrict__ part,
                  uint32_t *fb, uint32_t *rt) {
-    gamma_tile_lin_body<P>(n, d, force_fb, gg, tb, L, R, qt, Y1, part, fb, rt);
+    gamma_tile_lin_body<P, kSplit>(n, d, force_fb, vsplit, gg, tb, L, R, qt, Y1, part, fb, rt);
 }
 
 // Second chance for the endpoints that k_gamma_tile_lin could not scale from
@@ -2181,9 +2201,10 @@ k_gamma_tile_retry(int n, int d, GammaGeom gg, Tables tb, typename P::Store L,
 // ------------------------- a5 + a6: Gamma, in-tile part, tiles of any size
 // Generic form used when the lattice is smaller than the 12-bit tile of
 // k_gamma_tile (n < 12): the whole lattice is one tile of bT = n bits.
-// Workgroup = full-mask tile H (the low bT bits vary; entry x = reg * 256 + t).
-// L(H + x) and Rp(H + x) stay in registers for the whole workgroup; every
-// endpoint v not in H is served in turn:
+// Workgroup = full-mask tile H (the low bT bits vary; entry x = reg * 256 + t)
+// and, when the lattice is that one tile, one endpoint (vsplit = n workgroups;
+// otherwise vsplit = 1). L(H + x) and Rp(H + x) stay in registers for the
+// whole workgroup; each of its endpoints v not in H is served in turn:
 //   g_v(S) = q(|S|) L(S) Rp(S + v) for S = H + x. For v a tile bit, x runs
 //   over the entries without bit v and Rp(S + v) is the partner entry: the
 //   same thread's register when v is a register bit, else read through LDS.
@@ -2199,7 +2220,7 @@ k_gamma_tile_retry(int n, int d, GammaGeom gg, Tables tb, typename P::Store L,
 // writes of neighbouring tiles.
 template <class P, int RB>
 __global__ void __launch_bounds__(kThreads)
-k_gamma_tile_gen(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Store L,
+k_gamma_tile_gen(int n, int d, int bT, int vsplit, GammaGeom gg, Tables tb, typename P::Store L,
              typename P::Store R, const typename P::V *__restrict__ qt,
              typename P::V *__restrict__ Y1) {
     using V = typename P::V;
@@ -2215,8 +2236,12 @@ k_gamma_tile_gen(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Stor
     const int lb = bT < 8 ? bT : 8;          // thread bits of the tile
     const int hbits = n - bT;
     const uint32_t nblk = 1u << hbits;
-    uint32_t H = blockIdx.x;
-    if (nblk >= 64) H = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
+    // vsplit workgroups share a tile, workgroup v0 taking the endpoints
+    // v = v0 (mod vsplit)
+    const uint32_t blk = blockIdx.x / (uint32_t)vsplit;
+    const int v0 = (int)(blockIdx.x % (uint32_t)vsplit);
+    uint32_t H = blk;
+    if (nblk >= 64) H = (blk & 7) * (nblk >> 3) + (blk >> 3);
     const uint64_t Hf = (uint64_t)H << bT;
     for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
     for (uint32_t x = t; x < gg.KT; x += kThreads) seedT[x] = tb.seedmask[x];
@@ -2244,8 +2269,9 @@ k_gamma_tile_gen(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Stor
             Rr[r] = P::decode_raw(r0[r]);
         }
     }
-    int vn = bT;                              // next endpoint above the tile, not in H
-    while (vn < n && ((Hf >> vn) & 1)) ++vn;
+    int vn = v0;                              // next endpoint above the tile, not in H
+    while (vn < bT) vn += vsplit;
+    while (vn < n && ((Hf >> vn) & 1)) vn += vsplit;
     if (vn < n) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -2255,7 +2281,7 @@ k_gamma_tile_gen(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Stor
     }
     __syncthreads();
     const uint32_t *bn = sbin;
-    for (int v = 0; v < n; ++v) {
+    for (int v = v0; v < n; v += vsplit) {
         const bool low = v < bT;
         if (!low && ((Hf >> v) & 1)) continue;
         if (low && v < lb) {
@@ -2300,8 +2326,8 @@ k_gamma_tile_gen(int n, int d, int bT, GammaGeom gg, Tables tb, typename P::Stor
                 if (full || x < T)
                     g[r] = P::mul_raw(sq[pc[r]], P::mul_raw(Lr[r], P::decode_raw(Rv[r])));
             }
-            vn = v + 1;                       // prefetch the next endpoint's Rp tile
-            while (vn < n && ((Hf >> vn) & 1)) ++vn;
+            vn = v + vsplit;                  // prefetch the next endpoint's Rp tile
+            while (vn < n && ((Hf >> vn) & 1)) vn += vsplit;
             if (vn < n) {
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
@@ -2653,8 +2679,9 @@ k_edges(int n, uint32_t K, const uint32_t *__restrict__ famask,
 }
 
 // -------------------------------------------------------- invariants
-// Per tile H and in-tile layer l: sum of L(S) Rp(S); then per layer k of
-// the whole lattice. Every layer sum must equal L(V).
+// Per tile H (blockIdx.x) and in-tile layer l (blockIdx.y): sum of
+// L(S) Rp(S); then per layer k of the whole lattice. Every layer sum must
+// equal L(V).
 template <class P>
 __global__ void __launch_bounds__(kThreads)
 k_inv1(int n, int bL, Tables tb, typename P::Store L, typename P::Store R,
@@ -2662,17 +2689,16 @@ k_inv1(int n, int bL, Tables tb, typename P::Store L, typename P::Store R,
     using V = typename P::V;
     __shared__ V red[kThreads];
     const uint64_t Hf = (uint64_t)blockIdx.x << bL;
+    const int l = blockIdx.y;
     const int t = threadIdx.x;
     auto add = [](V a, V b) { return P::add(a, b); };
-    for (int l = 0; l <= bL; ++l) {
-        V acc = P::zero();
-        for (uint32_t idx = tb.loff[l] + t; idx < tb.loff[l + 1]; idx += kThreads) {
-            const uint64_t S = Hf | tb.lorder[idx];
-            acc = P::add(acc, P::mul(P::load(L, S), P::load(R, S)));
-        }
-        V s = block_reduce(acc, red, add);
-        if (t == 0) part[(size_t)blockIdx.x * (bL + 1) + l] = s;
+    V acc = P::zero();
+    for (uint32_t idx = tb.loff[l] + t; idx < tb.loff[l + 1]; idx += kThreads) {
+        const uint64_t S = Hf | tb.lorder[idx];
+        acc = P::add(acc, P::mul(P::load(L, S), P::load(R, S)));
     }
+    V s = block_reduce(acc, red, add);
+    if (t == 0) part[(size_t)blockIdx.x * (bL + 1) + l] = s;
 }
 
 template <class P>
@@ -3185,10 +3211,24 @@ static hipError_t launch_gamma_edges(const LatticeArgs &a, const typename P::Sto
             const unsigned nblkG = 1u << (n - 12);
             allow_big_lds<k_gamma_tile<P>>();
             if (a.lin_mode) {
-                allow_big_lds<k_gamma_tile_lin<P>>();
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile_lin<P>), dim3(nblkG),
-                                   dim3(kThreads), sm, st, n, d, a.lin_mode == 2 ? 1 : 0, gg, tb,
-                                   L, R, (const V *)qt, Y1, part, a.fbG, a.rtG);
+                // few tiles: their endpoints are split over several
+                // workgroups, so that about 512 run (a larger target, 1536,
+                // made n = 22 slower: the split form spills more registers
+                // and repeats the tile's set-up)
+                const unsigned vsplit =
+                    std::min((unsigned)n, std::max(1u, (512u + nblkG - 1) / nblkG));
+                if (vsplit > 1) {
+                    allow_big_lds<k_gamma_tile_lin<P, true>>();
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile_lin<P, true>),
+                                       dim3(nblkG * vsplit), dim3(kThreads), sm, st, n, d,
+                                       a.lin_mode == 2 ? 1 : 0, (int)vsplit, gg, tb, L, R,
+                                       (const V *)qt, Y1, part, a.fbG, a.rtG);
+                } else {
+                    allow_big_lds<k_gamma_tile_lin<P, false>>();
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile_lin<P, false>), dim3(nblkG),
+                                       dim3(kThreads), sm, st, n, d, a.lin_mode == 2 ? 1 : 0, 1,
+                                       gg, tb, L, R, (const V *)qt, Y1, part, a.fbG, a.rtG);
+                }
                 BN_CHECK_LAUNCH();
                 rec(7);
                 allow_big_lds<k_gamma_tile_retry<P>>();
@@ -3208,12 +3248,14 @@ static hipError_t launch_gamma_edges(const LatticeArgs &a, const typename P::Sto
             const int bT = a.bG;
             const size_t sm = sizeof(V) * ((size_t)1 << bT) + 33 * 33 * 4 + (size_t)gg.KT * 4 +
                               (size_t)gg.npat * 2;
-            const dim3 g(1u << (n - bT));
+            // a lattice of one tile: one workgroup per endpoint
+            const int vsplit = n == bT ? n : 1;
+            const dim3 g((1u << (n - bT)) * (unsigned)vsplit);
             const int RB = bT > 8 ? bT - 8 : 0;
 #define BN_GTILE(rb)                                                                           \
     allow_big_lds<k_gamma_tile_gen<P, rb>>();                                                  \
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gamma_tile_gen<P, rb>), g, dim3(kThreads), sm, st, n, \
-                       d, bT, gg, tb, L, R, (const V *)qt, Y1)
+                       d, bT, vsplit, gg, tb, L, R, (const V *)qt, Y1)
             switch (RB) {
                 case 0: BN_GTILE(0); break;
                 case 1: BN_GTILE(1); break;
@@ -3268,8 +3310,8 @@ static hipError_t launch_gamma_edges(const LatticeArgs &a, const typename P::Sto
     int bI = 12;
     if (a.bG != 12) {
         bI = a.bL;
-        hipLaunchKernelGGL(k_inv1<P>, dim3(1u << nh), dim3(kThreads), 0, st, n, a.bL, tb, L, R,
-                           part);
+        hipLaunchKernelGGL(k_inv1<P>, dim3(1u << nh, a.bL + 1), dim3(kThreads), 0, st, n, a.bL,
+                           tb, L, R, part);
         BN_CHECK_LAUNCH();
     }
     hipLaunchKernelGGL(k_inv2<P>, dim3(n + 1), dim3(kThreads), 0, st, n, bI, (const V *)part,
