@@ -2597,7 +2597,11 @@ k_gamma_high1_12(int n, int d, uint32_t K, GammaGeom gg, Tables tb,
 }
 
 // Level B, workgroup (v, seed): for each a-bit pattern p and each output
-// pattern y over the remaining hB bits, the superset sum over y' of y.
+// pattern y over the remaining hB bits, the superset sum over y' of y. With
+// hB <= 6 a wave takes 64 / 2^hB patterns p at a time, 2^hB lanes each: lane
+// y of a pattern loads entry y of its row (coalesced loads) and the downward
+// zeta over the hB bits runs across those lanes by shuffles. Larger hB
+// (n = 31) sums each output's supersets in turn.
 template <class P>
 __global__ void __launch_bounds__(kThreads)
 k_gamma_highB(int n, int d, int a, uint32_t KA, uint32_t K, GammaGeom gg, Tables tb,
@@ -2616,6 +2620,25 @@ k_gamma_highB(int n, int d, int a, uint32_t KA, uint32_t K, GammaGeom gg, Tables
     const int tr = d - sigma;
     const uint32_t ny = 1u << hB;
     const V *base = Y2 + gg.y2off[v];
+    if (hB <= 6) {
+        // lane = (pattern slot, y): 64 / 2^hB patterns per wave step
+        const uint32_t lane = t & 63, y = lane & (ny - 1), sub = lane >> hB;
+        const uint32_t ppw = 64u >> hB;
+        for (uint32_t p0 = (t >> 6) * ppw; p0 < KA; p0 += (kThreads / 64) * ppw) {
+            const uint32_t pi = p0 + sub;
+            const uint32_t p = pi < KA ? tb.pat[pi] : 0u;
+            const int pp = __popc(p);
+            const bool need = pi < KA && pp <= tr;
+            V x = need ? base[(((size_t)s * KA + pi) << hB) + y] : P::zero();
+            for (int b = 0; b < hB; ++b) {
+                const V o = shfl_xor_v(x, 1 << b);
+                if (!((y >> b) & 1)) x = P::add(x, o);
+            }
+            if (need && pp + __popc(y) <= tr)
+                gam[(size_t)v * K + out_rank(bn, N, sigma, cl, p | (y << a), bv)] = x;
+        }
+        return;
+    }
     for (uint32_t idx = t; idx < KA * ny; idx += kThreads) {
         const uint32_t pi = idx / ny;
         const uint32_t y = idx - pi * ny;
@@ -2701,23 +2724,29 @@ k_inv1(int n, int bL, Tables tb, typename P::Store L, typename P::Store R,
     if (t == 0) part[(size_t)blockIdx.x * (bL + 1) + l] = s;
 }
 
+// Workgroup (k, c): the layer-k sum over the c-th of kInvChunks ranges of
+// tiles, to layer[k * kInvChunks + c]; k_finalize adds the ranges in order.
+constexpr int kInvChunks = 32;
 template <class P>
 __global__ void __launch_bounds__(kThreads)
 k_inv2(int n, int bL, const typename P::V *__restrict__ part, typename P::V *__restrict__ layer) {
     using V = typename P::V;
     __shared__ V red[kThreads];
     const int k = blockIdx.x;
+    const int c = blockIdx.y;
     const int t = threadIdx.x;
     const uint32_t ntile = 1u << (n - bL);
+    const uint32_t per = (ntile + kInvChunks - 1) / kInvChunks;
+    const uint32_t h0 = c * per, h1 = min(ntile, h0 + per);
     auto add = [](V a, V b) { return P::add(a, b); };
     V acc = P::zero();
-    for (uint32_t H = t; H < ntile; H += kThreads) {
+    for (uint32_t H = h0 + t; H < h1; H += kThreads) {
         const int l = k - __popc(H);
         if (l < 0 || l > bL) continue;
         acc = P::add(acc, part[(size_t)H * (bL + 1) + l]);
     }
     V s = block_reduce(acc, red, add);
-    if (t == 0) layer[k] = s;
+    if (t == 0) layer[k * kInvChunks + c] = s;
 }
 
 // diag: [0] log L(V), [1] max residual, [2] saturated, [3] flushed,
@@ -2736,7 +2765,11 @@ __global__ void k_finalize(int n, typename P::Store L, typename P::Store R,
     for (int k = 0; k < 2 * n; ++k) g += gauge_exp[k];
     const double rLR = fabs(P::log_ratio(P::load(R, 0), LV));
     double rl = 0.0;
-    for (int k = 0; k <= n; ++k) rl = fmax(rl, fabs(P::log_ratio(layer[k], LV)));
+    for (int k = 0; k <= n; ++k) {
+        V lk = layer[k * kInvChunks];
+        for (int c = 1; c < kInvChunks; ++c) lk = P::add(lk, layer[k * kInvChunks + c]);
+        rl = fmax(rl, fabs(P::log_ratio(lk, LV)));
+    }
     double re = 0.0;
     for (int v = 0; v < n; ++v) re = fmax(re, resid[v]);
     diag[0] = P::to_log(LV) + g * 0.69314718055994530942;
@@ -3314,8 +3347,8 @@ static hipError_t launch_gamma_edges(const LatticeArgs &a, const typename P::Sto
                            tb, L, R, part);
         BN_CHECK_LAUNCH();
     }
-    hipLaunchKernelGGL(k_inv2<P>, dim3(n + 1), dim3(kThreads), 0, st, n, bI, (const V *)part,
-                       layer);
+    hipLaunchKernelGGL(k_inv2<P>, dim3(n + 1, kInvChunks), dim3(kThreads), 0, st, n, bI,
+                       (const V *)part, layer);
     BN_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_finalize<P>, dim3(1), dim3(64), 0, st, n, L, R, (const V *)layer,
                        (const double *)a.resid, (const double *)a.gauge_exp,

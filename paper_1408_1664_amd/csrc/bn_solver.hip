@@ -223,7 +223,7 @@ static Plan plan_of(int n, int d_in, int m, bn_precision prec, bool with_data, b
     P.o_cnt = take(4 * 8);
     P.o_diag = take(16 * 8);
     P.o_resid = take(32 * 8);
-    P.o_layer = take(33 * V);
+    P.o_layer = take(33 * 32 * V);     // layer sums of L(S) Rp(S), 32 tile ranges each
     P.o_qt = take(32 * V);
     P.o_gexp = take(64 * 8);
     P.o_logp = take((size_t)n * P.K * 8);
