@@ -449,6 +449,9 @@ def main():
               f"phases {r['phases_ms']}", file=sys.stderr, flush=True)
     serve = None
     if not args.no_serving:
+        # the lattice runs above leave their workspaces in torch's cache;
+        # the server allocates its own device arena
+        torch.cuda.empty_cache()
         serve = serving(bn, datagen)
         print(f"# serving: {serve['closed_loop']['solves_per_s']:.0f} solves/s saturated, "
               f"open-loop p50/p99 {[(round(o['p50_ms'], 2), round(o['p99_ms'], 2)) for o in serve['open_loop']]}",
