@@ -1563,6 +1563,43 @@ k_bwd(int n, int bL, int h, uint32_t hoff, Tables tb, typename P::Store alpha,
 }
 
 // ---------------------------------------- a5 + a6: Gamma, in-tile part
+// Layout of Y1_v (K(bv, d) ranks x 2^hv values of Hc). The ranks below
+// kg4 (K(bv, d) rounded down to a multiple of 4) sit in groups of four: group
+// j holds, for every Hc, the values of ranks 4j .. 4j + 3 side by side. A
+// Gamma tile workgroup writes one Hc of every rank, so its stores leave as
+// 32-byte runs instead of single 8-byte values. The ranks from kg4 on follow
+// as plain rows of 2^hv values.
+__device__ __forceinline__ size_t y1_at(uint32_t rank, uint64_t Hc, int hv, uint32_t kg4) {
+    return rank < kg4 ? ((((size_t)rank >> 2) << (hv + 2)) | ((size_t)Hc << 2) | (rank & 3u))
+                      : (((size_t)rank << hv) + Hc);
+}
+// distance between the entries of consecutive Hc of one rank
+__device__ __forceinline__ uint32_t y1_stride(uint32_t rank, uint32_t kg4) {
+    return rank < kg4 ? 4u : 1u;
+}
+// Workgroup order of the kernels that read Y1 rows: a workgroup's index
+// within endpoint v, local (rank-major: s * 2^hB + Ht), becomes the
+// (rank, Ht) item it takes, such that the four ranks of a group (same Ht)
+// run 8 workgroups apart, on one XCD, where its L2 serves the group's
+// 32-byte runs to all four. A bijection on [0, K(bv, d) 2^hB): whole octets
+// of (group, Ht) pairs first, then the rest of the grouped ranks with the
+// four ranks side by side, then the plain rows unchanged.
+__device__ __forceinline__ uint32_t y1_reader_item(uint32_t local, int hB, uint32_t kg4) {
+    const uint32_t G = (kg4 >> 2) << hB;        // (group, Ht) pairs
+    const uint32_t full = (G >> 3) << 5;        // locals of whole octets
+    if (local >= 4 * G) return local;
+    uint32_t gH, q;
+    if (local < full) {
+        q = (local >> 3) & 3u;
+        gH = ((local >> 5) << 3) | (local & 7u);
+    } else {
+        const uint32_t x = local - full;
+        q = x & 3u;
+        gH = ((G >> 3) << 3) + (x >> 2);
+    }
+    return ((((gH >> hB) << 2) | q) << hB) | (gH & ((1u << hB) - 1u));
+}
+
 // In-register downward zeta step over register bit q of NR = 2^RB entries,
 // skipped when that register bit carries the endpoint itself.
 template <class P, int NR>
@@ -1755,7 +1792,7 @@ __device__ __forceinline__ void gamma_tile(int n, int d, const GammaGeom &gg, co
                     rank += C(sbin, p, ++k);
                 }
             }
-            dst[((size_t)rank << hv) + Hc] = P::norm_v(gb[padx(msk)]);
+            dst[y1_at(rank, Hc, hv, gg.kg4[v])] = P::norm_v(gb[padx(msk)]);
         }
         __syncthreads();
     }
@@ -2030,7 +2067,7 @@ gamma_tile_lin_body(int n, int d, int force_fb, int vsplit, GammaGeom gg, Tables
                         rank += C(sbin, p, ++k);
                     }
                 }
-                dst[((size_t)rank << hv) + Hc] = P::from_lin(gb[padx(msk)], T);
+                dst[y1_at(rank, Hc, hv, gg.kg4[v])] = P::from_lin(gb[padx(msk)], T);
             }
         }
         __syncthreads();
@@ -2193,7 +2230,7 @@ k_gamma_tile_retry(int n, int d, GammaGeom gg, Tables tb, typename P::Store L,
                     rank += C(sbin, p, ++k);
                 }
             }
-            dst[((size_t)rank << hv) + Hc] = P::from_lin(gb[padx(msk)], T);
+            dst[y1_at(rank, Hc, hv, gg.kg4[v])] = P::from_lin(gb[padx(msk)], T);
         }
     }
 }
@@ -2383,7 +2420,7 @@ k_gamma_tile_gen(int n, int d, int bT, int vsplit, GammaGeom gg, Tables tb, type
                     rank += C(bn, p, ++k);
                 }
             }
-            dst[((size_t)rank << hv) + Hc] = P::norm_v(gb[msk]);
+            dst[y1_at(rank, Hc, hv, gg.kg4[v])] = P::norm_v(gb[msk]);
         }
         __syncthreads();
     }
@@ -2432,7 +2469,7 @@ k_gamma_high1(int n, int d, uint32_t K, GammaGeom gg, Tables tb,
     V *vec = reinterpret_cast<V *>(smem);
     const int N = n - 1;
     const int v = find_v(gg.blk1, n, blockIdx.x);
-    const uint32_t s = blockIdx.x - gg.blk1[v];
+    const uint32_t s = y1_reader_item(blockIdx.x - gg.blk1[v], 0, gg.kg4[v]);
     const int t = threadIdx.x;
     const uint32_t *bn = tb.binom;
     const int bv = gg.bv[v], hv = gg.hv[v];
@@ -2440,8 +2477,9 @@ k_gamma_high1(int n, int d, uint32_t K, GammaGeom gg, Tables tb,
     uint32_t cl;
     seed_of(bn, bv, s, &sigma, &cl);
     const int tr = d - sigma;
-    const V *src = Y1 + gg.y1off[v] + ((size_t)s << hv);
-    for (uint32_t x = t; x < (1u << hv); x += kThreads) vec[x] = src[x];
+    const V *src = Y1 + gg.y1off[v] + y1_at(s, 0, hv, gg.kg4[v]);
+    const uint32_t st = y1_stride(s, gg.kg4[v]);
+    for (uint32_t x = t; x < (1u << hv); x += kThreads) vec[x] = src[(size_t)x * st];
     __syncthreads();
     for (int j = 0; j < hv; ++j) {
         const uint32_t cntj = Kcount(bn, j, d);  // walk the d-table, skip > tr
@@ -2474,9 +2512,9 @@ k_gamma_highA(int n, int d, int a, uint32_t KA, GammaGeom gg, Tables tb,
     extern __shared__ unsigned char smem[];
     V *vec = reinterpret_cast<V *>(smem);
     const int v = find_v(gg.blkA, n, blockIdx.x);
-    const uint32_t local = blockIdx.x - gg.blkA[v];
     const int bv = gg.bv[v], hv = gg.hv[v];
     const int hB = hv - a;
+    const uint32_t local = y1_reader_item(blockIdx.x - gg.blkA[v], hB, gg.kg4[v]);
     const uint32_t Ht = local & ((1u << hB) - 1);
     const uint32_t s = local >> hB;
     const int t = threadIdx.x;
@@ -2485,8 +2523,9 @@ k_gamma_highA(int n, int d, int a, uint32_t KA, GammaGeom gg, Tables tb,
     uint32_t cl;
     seed_of(bn, bv, s, &sigma, &cl);
     const int tr = d - sigma;
-    const V *src = Y1 + gg.y1off[v] + ((size_t)s << hv) + ((size_t)Ht << a);
-    for (uint32_t x = t; x < (1u << a); x += kThreads) vec[x] = src[x];
+    const V *src = Y1 + gg.y1off[v] + y1_at(s, (uint64_t)Ht << a, hv, gg.kg4[v]);
+    const uint32_t st = y1_stride(s, gg.kg4[v]);
+    for (uint32_t x = t; x < (1u << a); x += kThreads) vec[x] = src[(size_t)x * st];
     __syncthreads();
     for (int j = 0; j < a; ++j) {
         const uint32_t cntj = Kcount(bn, j, d);
@@ -2513,13 +2552,9 @@ k_gamma_highA(int n, int d, int a, uint32_t KA, GammaGeom gg, Tables tb,
 // computed too and never read. No pattern table, division or skip test per
 // update. Ends with a barrier.
 template <class P>
-__device__ __forceinline__ void dense_zeta_down12(const typename P::V *__restrict__ src,
-                                                  typename P::V *vec, uint32_t t) {
-    using V = typename P::V;
+__device__ __forceinline__ void dense_zeta_down12_regs(typename P::V (&g)[16],
+                                                       typename P::V *vec, uint32_t t) {
     constexpr int NR = 16;
-    V g[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) g[r] = src[(t << 4) | r];
     auto zeta4 = [&]() {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -2546,54 +2581,102 @@ __device__ __forceinline__ void dense_zeta_down12(const typename P::V *__restric
     __syncthreads();
 }
 
-// Level A for a = 12: the outputs of k_gamma_highA from the dense zeta.
 template <class P>
-__global__ void __launch_bounds__(kThreads)
-k_gamma_highA12(int n, uint32_t KA, GammaGeom gg, Tables tb,
-                const typename P::V *__restrict__ Y1, typename P::V *__restrict__ Y2) {
-    using V = typename P::V;
-    constexpr int a = 12;
-    extern __shared__ unsigned char smem[];
-    V *vec = reinterpret_cast<V *>(smem);   // 2^12 entries at padx indices
-    const int v = find_v(gg.blkA, n, blockIdx.x);
-    const uint32_t local = blockIdx.x - gg.blkA[v];
-    const int hv = gg.hv[v];
-    const int hB = hv - a;
-    const uint32_t Ht = local & ((1u << hB) - 1);
-    const uint32_t s = local >> hB;
-    const uint32_t t = threadIdx.x;
-    dense_zeta_down12<P>(Y1 + gg.y1off[v] + ((size_t)s << hv) + ((size_t)Ht << a), vec, t);
-    V *dst = Y2 + gg.y2off[v];
-    for (uint32_t pi = t; pi < KA; pi += kThreads)
-        dst[(((size_t)s * KA + pi) << hB) + Ht] = vec[padx(tb.pat[pi])];
+__device__ __forceinline__ void dense_zeta_down12(const typename P::V *__restrict__ src,
+                                                  uint32_t stride, typename P::V *vec,
+                                                  uint32_t t) {
+    typename P::V g[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) g[r] = src[(size_t)((t << 4) | r) * stride];
+    dense_zeta_down12_regs<P>(g, vec, t);
 }
 
-// One level with hv = 12 (every one-level endpoint when n = 25): the outputs
-// of k_gamma_high1 from the dense zeta.
-template <class P>
+// The FP32-scaled form of the dense 12-bit passes over the grouped ranks of
+// Y1: a workgroup loads the four ranks of a group at once (32 bytes per
+// entry, each byte read once) and runs the zeta for each in turn; the ranks
+// past the groups take one workgroup each. item: the workgroup's index within
+// endpoint v; the grouped items come first, (group, Ht) with Ht fastest.
+// Calls out(s, Ht) after the zeta of rank s has left vec (ends with a barrier).
+template <class Out>
+__device__ __forceinline__ void dense_zeta_down12_x4(const X32 *__restrict__ Y1v, int hv, int hB,
+                                                     uint32_t kg4, uint32_t item, X32 *vec,
+                                                     uint32_t t, Out out) {
+    const uint32_t G = (kg4 >> 2) << hB;
+    const uint32_t hmask = (1u << hB) - 1u;
+    if (item < G) {
+        const uint32_t s0 = (item >> hB) << 2, Ht = item & hmask;
+        const uint4 *src = reinterpret_cast<const uint4 *>(Y1v + y1_at(s0, (uint64_t)Ht << 12, hv, kg4));
+        uint4 raw[16][2];                     // entry (t << 4) | r: ranks s0, s0 + 1 | s0 + 2, s0 + 3
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            raw[r][0] = src[2 * ((t << 4) | r)];
+            raw[r][1] = src[2 * ((t << 4) | r) + 1];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            X32 g[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint4 w = raw[r][q >> 1];
+                g[r] = (q & 1) ? X32{__uint_as_float(w.z), (int)w.w}
+                               : X32{__uint_as_float(w.x), (int)w.y};
+            }
+            dense_zeta_down12_regs<PolX32>(g, vec, t);
+            out(s0 + q, Ht);
+            __syncthreads();                  // vec is read by out()
+        }
+    } else {
+        const uint32_t x = item - G;
+        const uint32_t s = kg4 + (x >> hB), Ht = x & hmask;
+        dense_zeta_down12<PolX32>(Y1v + y1_at(s, (uint64_t)Ht << 12, hv, kg4), 1u, vec, t);
+        out(s, Ht);
+    }
+}
+
+// Level A for a = 12, FP32-scaled form: the outputs of k_gamma_highA from
+// the dense zeta, over groups of ranks.
+__global__ void __launch_bounds__(kThreads)
+k_gamma_highA12(int n, uint32_t KA, GammaGeom gg, Tables tb, const X32 *__restrict__ Y1,
+                   X32 *__restrict__ Y2) {
+    extern __shared__ unsigned char smem[];
+    X32 *vec = reinterpret_cast<X32 *>(smem);   // 2^12 entries at padx indices
+    const int v = find_v(gg.blkAx4, n, blockIdx.x);
+    const int hB = gg.hv[v] - 12;
+    const uint32_t t = threadIdx.x;
+    X32 *dst = Y2 + gg.y2off[v];
+    dense_zeta_down12_x4(Y1 + gg.y1off[v], gg.hv[v], hB, gg.kg4[v], blockIdx.x - gg.blkAx4[v],
+                         vec, t, [&](uint32_t s, uint32_t Ht) {
+                             for (uint32_t pi = t; pi < KA; pi += kThreads)
+                                 dst[(((size_t)s * KA + pi) << hB) + Ht] = vec[padx(tb.pat[pi])];
+                         });
+}
+
+// One level with hv = 12 (every one-level endpoint when n = 25), FP32-scaled
+// form: the outputs of k_gamma_high1 from the dense zeta, over groups of ranks.
 __global__ void __launch_bounds__(kThreads)
 k_gamma_high1_12(int n, int d, uint32_t K, GammaGeom gg, Tables tb,
-                 const typename P::V *__restrict__ Y1, typename P::V *__restrict__ gam) {
-    using V = typename P::V;
+                    const X32 *__restrict__ Y1, X32 *__restrict__ gam) {
     extern __shared__ unsigned char smem[];
-    V *vec = reinterpret_cast<V *>(smem);   // 2^12 entries at padx indices
+    X32 *vec = reinterpret_cast<X32 *>(smem);   // 2^12 entries at padx indices
     const int N = n - 1;
-    const int v = find_v(gg.blk1, n, blockIdx.x);
-    const uint32_t s = blockIdx.x - gg.blk1[v];
+    const int v = find_v(gg.blk1x4, n, blockIdx.x);
     const uint32_t t = threadIdx.x;
     const uint32_t *bn = tb.binom;
     const int bv = gg.bv[v];
-    int sigma;
-    uint32_t cl;
-    seed_of(bn, bv, s, &sigma, &cl);
-    const int tr = d - sigma;
-    dense_zeta_down12<P>(Y1 + gg.y1off[v] + ((size_t)s << 12), vec, t);
     const uint32_t npat = Kcount(bn, 12, d);
-    for (uint32_t idx = t; idx < npat; idx += kThreads) {
-        const uint32_t x = tb.pat[idx];
-        if (__popc(x) > tr) continue;
-        gam[(size_t)v * K + out_rank(bn, N, sigma, cl, x, bv)] = vec[padx(x)];
-    }
+    dense_zeta_down12_x4(Y1 + gg.y1off[v], 12, 0, gg.kg4[v], blockIdx.x - gg.blk1x4[v], vec, t,
+                         [&](uint32_t s, uint32_t) {
+                             int sigma;
+                             uint32_t cl;
+                             seed_of(bn, bv, s, &sigma, &cl);
+                             const int tr = d - sigma;
+                             for (uint32_t idx = t; idx < npat; idx += kThreads) {
+                                 const uint32_t x = tb.pat[idx];
+                                 if (__popc(x) > tr) continue;
+                                 gam[(size_t)v * K + out_rank(bn, N, sigma, cl, x, bv)] =
+                                     vec[padx(x)];
+                             }
+                         });
 }
 
 // Level B, workgroup (v, seed): for each a-bit pattern p and each output
@@ -3305,11 +3388,13 @@ static hipError_t launch_gamma_edges(const LatticeArgs &a, const typename P::Sto
             bool all12 = std::is_same<P, PolX32>::value;
             for (int v = 0; v < n && all12; ++v)
                 if (gg.blk1[v + 1] > gg.blk1[v]) all12 = gg.hv[v] == 12;
-            if (all12)
-                hipLaunchKernelGGL(k_gamma_high1_12<P>, dim3(gg.blk1[n]), dim3(kThreads),
-                                   sizeof(V) * (4096 + 256), st, n, d, a.K, gg, tb,
-                                   (const V *)Y1, gam);
-            else
+            if constexpr (std::is_same<P, PolX32>::value) {
+                if (all12)
+                    hipLaunchKernelGGL(k_gamma_high1_12, dim3(gg.blk1x4[n]), dim3(kThreads),
+                                       sizeof(V) * (4096 + 256), st, n, d, a.K, gg, tb,
+                                       (const V *)Y1, gam);
+            }
+            if (!all12)
                 hipLaunchKernelGGL(k_gamma_high1<P>, dim3(gg.blk1[n]), dim3(kThreads),
                                    sizeof(V) << gg.hmax1, st, n, d, a.K, gg, tb, (const V *)Y1,
                                    gam);
@@ -3319,11 +3404,16 @@ static hipError_t launch_gamma_edges(const LatticeArgs &a, const typename P::Sto
             // dense 12-bit form for the FP32-scaled system; the log form keeps the
             // truncated pass (its log-adds are costly enough that the skipped
             // entries matter more than the indexing)
-            if (a.aG == 12 && std::is_same<P, PolX32>::value)
-                hipLaunchKernelGGL(k_gamma_highA12<P>, dim3(gg.blkA[n]), dim3(kThreads),
-                                   sizeof(V) * (4096 + 256), st, n, a.KA, gg, tb, (const V *)Y1,
-                                   Y2);
-            else
+            bool dense = false;
+            if constexpr (std::is_same<P, PolX32>::value) {
+                if (a.aG == 12) {
+                    dense = true;
+                    hipLaunchKernelGGL(k_gamma_highA12, dim3(gg.blkAx4[n]), dim3(kThreads),
+                                       sizeof(V) * (4096 + 256), st, n, a.KA, gg, tb,
+                                       (const V *)Y1, Y2);
+                }
+            }
+            if (!dense)
                 hipLaunchKernelGGL(k_gamma_highA<P>, dim3(gg.blkA[n]), dim3(kThreads),
                                    sizeof(V) << a.aG, st, n, d, a.aG, a.KA, gg, tb,
                                    (const V *)Y1, Y2);

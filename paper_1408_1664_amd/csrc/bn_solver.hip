@@ -178,6 +178,7 @@ static Plan plan_of(int n, int d_in, int m, bn_precision prec, bool with_data, b
             g.hv[v] = N - g.bv[v];
             const uint64_t kg = kcount_u64(g.bv[v], d);
             g.y1off[v] = y1;
+            g.kg4[v] = (uint32_t)kg & ~3u;
             y1 += kg << g.hv[v];
             const bool two = g.hv[v] > P.aG;
             g.y2off[v] = y2;
@@ -185,6 +186,9 @@ static Plan plan_of(int n, int d_in, int m, bn_precision prec, bool with_data, b
             else hmax1 = std::max(hmax1, g.hv[v]);
             g.blk1[v + 1] = g.blk1[v] + (two ? 0 : (uint32_t)kg);
             g.blkA[v + 1] = g.blkA[v] + (two ? (uint32_t)(kg << (g.hv[v] - P.aG)) : 0);
+            const uint32_t items4 = g.kg4[v] / 4 + ((uint32_t)kg - g.kg4[v]);
+            g.blk1x4[v + 1] = g.blk1x4[v] + (two ? 0 : items4);
+            g.blkAx4[v + 1] = g.blkAx4[v] + (two ? items4 << (g.hv[v] - P.aG) : 0);
             g.blkB[v + 1] = g.blkB[v] + (two ? (uint32_t)kg : 0);
         }
         g.KT = P.KG;
