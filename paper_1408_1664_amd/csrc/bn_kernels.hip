@@ -2106,9 +2106,10 @@ k_gamma_tile_lin(int n, int d, int force_fb, int vsplit, GammaGeom gg, Tables tb
 // list). The scale now comes from the largest product of the tile, which
 // keeps Gamma_v(H + empty) finite; the outputs are stored only if every
 // needed one is at least 2^-1000, since the products that fell below 2^-1074
-// (at most 4096) then change none by more than 2^-62 of itself. Otherwise
-// (H, v) goes to the fallback list of k_gamma_tile_fb. Same layouts as
-// k_gamma_tile_lin, layout C for every thread.
+// (at most 4096) then change none by more than 2^-62 of itself. Outputs below
+// that get a third chance under the first scale (below); an endpoint with an
+// output valid under neither goes to the fallback list of k_gamma_tile_fb.
+// Same layouts as k_gamma_tile_lin, layout C for every thread.
 template <class P>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_gamma_tile_retry(int n, int d, GammaGeom gg, Tables tb, typename P::Store L,
@@ -2125,6 +2126,7 @@ k_gamma_tile_retry(int n, int d, GammaGeom gg, Tables tb, typename P::Store L,
     __shared__ V sq[32];
     __shared__ uint32_t offT1[34];
     __shared__ int smax;
+    __shared__ A sT2;
     const uint32_t t = threadIdx.x;
     for (int x = t; x < 33 * 33; x += kThreads) sbin[x] = tb.binom[x];
     for (uint32_t x = t; x < gg.KT; x += kThreads) seedT[x] = tb.seedmask[x];
@@ -2177,49 +2179,105 @@ k_gamma_tile_retry(int n, int d, GammaGeom gg, Tables tb, typename P::Store L,
         __syncthreads();
         const bool any = smax > -(1 << 29);
         const A T = P::anchor_high(smax);
-        double g[NR];
+        // downward zeta of the products under scale Ts over the tile bits
+        // but v, into gb (layout C for every thread)
+        auto zeta3 = [&](const A Ts) {
+            double g[NR];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) g[r] = P::prod2_lin(pv[r], P::one(), T);
+            for (int r = 0; r < NR; ++r) g[r] = P::prod2_lin(pv[r], P::one(), Ts);
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (v != q) lin_zeta_down<NR>(g, q);
+            for (int q = 0; q < 4; ++q)
+                if (v != q) lin_zeta_down<NR>(g, q);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) gb[padx((t << 4) | r)] = g[r];
-        __syncthreads();
+            for (int r = 0; r < NR; ++r) gb[padx((t << 4) | r)] = g[r];
+            __syncthreads();
 #pragma unroll
-        for (int r = 0; r < NR; ++r) g[r] = gb[padx((thi << 8) | (r << 4) | tlo)];
+            for (int r = 0; r < NR; ++r) g[r] = gb[padx((thi << 8) | (r << 4) | tlo)];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (v != 4 + q) lin_zeta_down<NR>(g, q);
+            for (int q = 0; q < 4; ++q)
+                if (v != 4 + q) lin_zeta_down<NR>(g, q);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) gb[padx((thi << 8) | (r << 4) | tlo)] = g[r];
-        __syncthreads();
+            for (int r = 0; r < NR; ++r) gb[padx((thi << 8) | (r << 4) | tlo)] = g[r];
+            __syncthreads();
 #pragma unroll
-        for (int r = 0; r < NR; ++r) g[r] = gb[padx((r << 8) | t)];
+            for (int r = 0; r < NR; ++r) g[r] = gb[padx((r << 8) | t)];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (v != 8 + q) lin_zeta_down<NR>(g, q);
+            for (int q = 0; q < 4; ++q)
+                if (v != 8 + q) lin_zeta_down<NR>(g, q);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) gb[padx((r << 8) | t)] = g[r];
-        __syncthreads();
+            for (int r = 0; r < NR; ++r) gb[padx((r << 8) | t)] = g[r];
+            __syncthreads();
+        };
+        zeta3(T);
         bool small = !(any && gb[padx(0)] <= 1.0e300);
         for (uint32_t si = t; si < gg.KT && !small; si += kThreads) {
             const uint32_t msk = seedT[si];
             if (low && ((msk >> v) & 1)) continue;
             small = !(gb[padx(msk)] >= 0x1p-1000);
         }
+        // Third chance for outputs below 2^-1000 under the largest product's
+        // scale: a pass under the scale of g_v(H + top) (every needed output
+        // holds that term, so it is at least about 2^-1000 there; an output
+        // that overflows there is at least 2^-1000 under the first scale when
+        // the two scales lie less than 2024 binary orders apart). Each needed
+        // output is taken from the pass where it is at least 2^-1000 and
+        // finite; an endpoint with an output valid in neither goes to
+        // k_gamma_tile_fb. Outputs of the first pass wait in registers
+        // (at most 4 per thread, K(12, d) <= 1024).
+        constexpr int kMaxOut = 4;
+        double keep1[kMaxOut];
+        A T2 = T;
+        bool two = false;
         if (__syncthreads_or(small ? 1 : 0)) {
-            if (t == 0) fb_push(fb, (H << 6) | (uint32_t)(v + 1));   // this endpoint only
-            continue;
+            bool ok = any && gg.KT <= kMaxOut * kThreads;
+            if (ok) {
+                // g_v(H + top): top = every tile bit but v, entry x_top of layout A
+                const uint32_t xtop = low ? (0xfffu & ~(1u << v)) : 0xfffu;
+                if (t == (xtop >> 4)) {
+                    A Tt{};
+                    V top = P::zero();
+#pragma unroll
+                    for (int r = 0; r < NR; ++r)
+                        if ((uint32_t)r == (xtop & 15u)) top = pv[r];
+                    smax = P::anchor_of(top, &Tt) ? 1 : 0;
+                    sT2 = Tt;
+                }
+                __syncthreads();
+                ok = smax != 0;
+                T2 = sT2;
+            }
+            if (ok) {
+#pragma unroll
+                for (int k = 0; k < kMaxOut; ++k) {
+                    const uint32_t si = t + k * kThreads;
+                    keep1[k] = si < gg.KT ? gb[padx(seedT[si])] : 0.0;
+                }
+                __syncthreads();                  // gb is rewritten by the second pass
+                zeta3(T2);
+                bool fail = false;
+#pragma unroll
+                for (int k = 0; k < kMaxOut; ++k) {
+                    const uint32_t si = t + k * kThreads;
+                    if (si >= gg.KT) continue;
+                    const uint32_t msk = seedT[si];
+                    if (low && ((msk >> v) & 1)) continue;
+                    const double y2 = gb[padx(msk)];
+                    fail = fail || !(keep1[k] >= 0x1p-1000 || (y2 >= 0x1p-1000 && y2 <= 1.0e300));
+                }
+                ok = __syncthreads_or(fail ? 1 : 0) == 0;
+            }
+            if (!ok) {
+                if (t == 0) fb_push(fb, (H << 6) | (uint32_t)(v + 1));   // this endpoint only
+                continue;
+            }
+            two = true;
         }
         const int hv = gg.hv[v];
         const uint32_t Hc = low ? H : (uint32_t)compress_bit(H, v - bT);
         V *dst = Y1 + gg.y1off[v];
-        for (uint32_t si = t; si < gg.KT; si += kThreads) {
-            const uint32_t msk = seedT[si];
+        auto rank_of = [&](uint32_t si, uint32_t msk) {
             uint32_t rank = si;
             if (low) {
-                if ((msk >> v) & 1) continue;
                 const uint32_t cm = (uint32_t)compress_bit(msk, v);
                 rank = offT1[__popc(cm)];
                 int k = 0;
@@ -2230,7 +2288,25 @@ k_gamma_tile_retry(int n, int d, GammaGeom gg, Tables tb, typename P::Store L,
                     rank += C(sbin, p, ++k);
                 }
             }
-            dst[y1_at(rank, Hc, hv, gg.kg4[v])] = P::from_lin(gb[padx(msk)], T);
+            return rank;
+        };
+        if (two) {
+#pragma unroll
+            for (int k = 0; k < kMaxOut; ++k) {
+                const uint32_t si = t + k * kThreads;
+                if (si >= gg.KT) break;
+                const uint32_t msk = seedT[si];
+                if (low && ((msk >> v) & 1)) continue;
+                const bool first = keep1[k] >= 0x1p-1000;
+                dst[y1_at(rank_of(si, msk), Hc, hv, gg.kg4[v])] =
+                    P::from_lin(first ? keep1[k] : gb[padx(msk)], first ? T : T2);
+            }
+        } else {
+            for (uint32_t si = t; si < gg.KT; si += kThreads) {
+                const uint32_t msk = seedT[si];
+                if (low && ((msk >> v) & 1)) continue;
+                dst[y1_at(rank_of(si, msk), Hc, hv, gg.kg4[v])] = P::from_lin(gb[padx(msk)], T);
+            }
         }
     }
 }
