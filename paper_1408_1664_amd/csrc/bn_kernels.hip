@@ -2709,6 +2709,89 @@ __device__ __forceinline__ void dense_zeta_down12_x4(const X32 *__restrict__ Y1v
     }
 }
 
+// Plain doubles for dense_zeta_down12_regs.
+struct Lin64 {
+    using V = double;
+    __device__ static inline V add(V a, V b) { return a + b; }
+};
+
+// Level A for a = 12 in the log form. The row's logarithms become plain
+// doubles under one scale, exp(x - M) 2^960 with M the row's largest (so the
+// sum of 4096 of them stays below 2^972), the dense 12-bit zeta runs in FP64
+// adds, and the outputs go back as logarithms. They are kept only if every
+// needed output (at most d - sigma ones) is at least 2^-1000: the values that
+// fell below 2^-1074 (at most 4096) then change none by more than 2^-62 of
+// itself. Otherwise the workgroup runs the truncated log-add pass of
+// k_gamma_highA on the row.
+__global__ void __launch_bounds__(kThreads)
+k_gamma_highA12_log(int n, int d, uint32_t KA, GammaGeom gg, Tables tb,
+                    const double *__restrict__ Y1, double *__restrict__ Y2) {
+    constexpr int a = 12;
+    extern __shared__ unsigned char smem[];
+    double *vec = reinterpret_cast<double *>(smem);   // 2^12 entries, padx or plain
+    __shared__ double red[kThreads];
+    const int v = find_v(gg.blkA, n, blockIdx.x);
+    const int bv = gg.bv[v], hv = gg.hv[v];
+    const int hB = hv - a;
+    const uint32_t local = y1_reader_item(blockIdx.x - gg.blkA[v], hB, gg.kg4[v]);
+    const uint32_t Ht = local & ((1u << hB) - 1);
+    const uint32_t s = local >> hB;
+    const uint32_t t = threadIdx.x;
+    const uint32_t *bn = tb.binom;
+    int sigma;
+    uint32_t cl;
+    seed_of(bn, bv, s, &sigma, &cl);
+    const int tr = d - sigma;
+    const double *src = Y1 + gg.y1off[v] + y1_at(s, (uint64_t)Ht << a, hv, gg.kg4[v]);
+    const uint32_t st = y1_stride(s, gg.kg4[v]);
+    double *dst = Y2 + gg.y2off[v];
+    auto out_at = [&](uint32_t pi) -> double & { return dst[(((size_t)s * KA + pi) << hB) + Ht]; };
+    double g[16];
+    double mx = -__builtin_huge_val();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        g[r] = src[(size_t)((t << 4) | r) * st];
+        mx = fmax(mx, g[r]);
+    }
+    mx = block_reduce(mx, red, [](double x, double y) { return fmax(x, y); });
+    if (!(mx > -1e300)) {                            // an empty row: every output is zero
+        for (uint32_t pi = t; pi < KA; pi += kThreads) out_at(pi) = -__builtin_huge_val();
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) g[r] = g[r] > -1e300 ? ldexp(exp(g[r] - mx), 960) : 0.0;
+    dense_zeta_down12_regs<Lin64>(g, vec, t);
+    bool small = false;
+    for (uint32_t pi = t; pi < KA; pi += kThreads) {
+        const uint32_t x = tb.pat[pi];
+        if (__popc(x) <= tr) small = small || !(vec[padx(x)] >= 0x1p-1000);
+    }
+    if (!__syncthreads_or(small ? 1 : 0)) {
+        const double off = mx - 960.0 * 0.69314718055994530942;
+        for (uint32_t pi = t; pi < KA; pi += kThreads) {
+            const double y = vec[padx(tb.pat[pi])];
+            out_at(pi) = y > 0.0 ? log(y) + off : -__builtin_huge_val();
+        }
+        return;
+    }
+    // the truncated log-add pass of k_gamma_highA
+    for (uint32_t x = t; x < (1u << a); x += kThreads) vec[x] = src[(size_t)x * st];
+    __syncthreads();
+    for (int j = 0; j < a; ++j) {
+        const uint32_t cntj = Kcount(bn, j, d);
+        const uint32_t tot = cntj << (a - 1 - j);
+        for (uint32_t idx = t; idx < tot; idx += kThreads) {
+            const uint32_t hi = idx / cntj;
+            const uint32_t p = tb.pat[idx - hi * cntj];
+            if (__popc(p) > tr) continue;
+            const uint32_t Tm = (hi << (j + 1)) | p;
+            vec[Tm] = PolLog::add(vec[Tm], vec[Tm | (1u << j)]);
+        }
+        __syncthreads();
+    }
+    for (uint32_t pi = t; pi < KA; pi += kThreads) out_at(pi) = vec[tb.pat[pi]];
+}
+
 // Level A for a = 12, FP32-scaled form: the outputs of k_gamma_highA from
 // the dense zeta, over groups of ranks.
 __global__ void __launch_bounds__(kThreads)
@@ -3487,6 +3570,14 @@ static hipError_t launch_gamma_edges(const LatticeArgs &a, const typename P::Sto
                     hipLaunchKernelGGL(k_gamma_highA12, dim3(gg.blkAx4[n]), dim3(kThreads),
                                        sizeof(V) * (4096 + 256), st, n, a.KA, gg, tb,
                                        (const V *)Y1, Y2);
+                }
+            }
+            if constexpr (std::is_same<P, PolLog>::value) {
+                if (a.aG == 12) {
+                    dense = true;
+                    hipLaunchKernelGGL(k_gamma_highA12_log, dim3(gg.blkA[n]), dim3(kThreads),
+                                       sizeof(double) * (4096 + 256), st, n, d, a.KA, gg, tb,
+                                       (const double *)Y1, (double *)Y2);
                 }
             }
             if (!dense)
