@@ -1839,10 +1839,14 @@ __device__ inline void lin_zeta_down(double *g, int q) {
 // every needed output Gamma_v(G_L) of the tile is a sum over supersets of
 // G_L that includes g_v(H + top), top = every tile bit but v. So the
 // products are scaled by one power of two (a log offset for the log-space
-// system) that puts g_v(H + top) near 2^-1000, and the downward zeta runs on
-// plain doubles: one FP64 add per step. Products far below g_v(H + top) may
-// lose bits to the subnormal range; that changes no output by more than
-// 2^-60 of itself. If Gamma_v(H + empty), the largest entry, overflows after
+// system) that puts g_v(H + top) near 2^-1000 (within 2^-1032 .. 2^-968 in the
+// FP32-scaled form, whose scales are multiples of 64), and the downward zeta
+// runs on plain doubles: one FP64 add per step. Products far below
+// g_v(H + top) may lose bits to the subnormal range, each at most 2^-1075;
+// over the at most 2^11 terms of an output (which is at least g_v(H + top))
+// that is at most 2^-32 of the output in the FP32-scaled form, below the
+// 2^-24 rounding of its stored significand, and 2^-64 in the log form. If
+// Gamma_v(H + empty), the largest entry, overflows after
 // the scaling, or g_v(H + top) is zero, the endpoint's outputs are not stored
 // and (H, v) goes to the list of k_gamma_tile_retry. force_fb sends every
 // tile to the fallback list of k_gamma_tile_fb, which recomputes all of its
