@@ -2725,10 +2725,10 @@ struct Lin64 {
 // adds, and the outputs go back as logarithms. They are kept only if every
 // needed output (at most d - sigma ones) is at least 2^-1000: the values that
 // fell below 2^-1074 (at most 4096) then change none by more than 2^-62 of
-// itself. Otherwise the workgroup runs the truncated log-add pass of
-// k_gamma_highA on the row.
+// itself. Otherwise, or always with force_trunc (tests), the workgroup runs
+// the truncated log-add pass of k_gamma_highA on the row.
 __global__ void __launch_bounds__(kThreads)
-k_gamma_highA12_log(int n, int d, uint32_t KA, GammaGeom gg, Tables tb,
+k_gamma_highA12_log(int n, int d, uint32_t KA, int force_trunc, GammaGeom gg, Tables tb,
                     const double *__restrict__ Y1, double *__restrict__ Y2) {
     constexpr int a = 12;
     extern __shared__ unsigned char smem[];
@@ -2770,7 +2770,7 @@ k_gamma_highA12_log(int n, int d, uint32_t KA, GammaGeom gg, Tables tb,
         const uint32_t x = tb.pat[pi];
         if (__popc(x) <= tr) small = small || !(vec[padx(x)] >= 0x1p-1000);
     }
-    if (!__syncthreads_or(small ? 1 : 0)) {
+    if (!__syncthreads_or(small || force_trunc ? 1 : 0)) {
         const double off = mx - 960.0 * 0.69314718055994530942;
         for (uint32_t pi = t; pi < KA; pi += kThreads) {
             const double y = vec[padx(tb.pat[pi])];
@@ -3577,11 +3577,13 @@ static hipError_t launch_gamma_edges(const LatticeArgs &a, const typename P::Sto
                 }
             }
             if constexpr (std::is_same<P, PolLog>::value) {
-                if (a.aG == 12) {
+                // plain doubles under a scale, as the linear tiles (off with them)
+                if (a.aG == 12 && a.lin_mode != 0) {
                     dense = true;
                     hipLaunchKernelGGL(k_gamma_highA12_log, dim3(gg.blkA[n]), dim3(kThreads),
-                                       sizeof(double) * (4096 + 256), st, n, d, a.KA, gg, tb,
-                                       (const double *)Y1, (double *)Y2);
+                                       sizeof(double) * (4096 + 256), st, n, d, a.KA,
+                                       a.lin_mode == 2 ? 1 : 0, gg, tb, (const double *)Y1,
+                                       (double *)Y2);
                 }
             }
             if (!dense)

@@ -61,8 +61,11 @@ def _bounds(P, d, tol):
 
 
 @pytest.mark.parametrize("prec,tol,lin,fused", [("fp64", 1e-10, None, "0"),
+                                                ("fp64", 1e-10, "force", "0"),
+                                                ("fp64", 1e-10, "0", "0"),
                                                 ("fp32", 1e-5, None, "0"),
                                                 ("fp32", 1e-5, "0", "0"),
+                                                ("fp32", 1e-5, "force", "0"),
                                                 ("fp32", 1e-5, None, "1")])
 def test_n27_prefix_of_n30_against_oracle(prec, tol, lin, fused, monkeypatch):
     ref = json.load(open(os.path.join(GOLD, "oracle_n30_binary_m500_d3_first27.json")))
