@@ -2661,6 +2661,39 @@ __device__ __forceinline__ void dense_zeta_down12_regs(typename P::V (&g)[16],
     __syncthreads();
 }
 
+// The same zeta from layout C (g[r] = entry r * 256 + t, so that the loads
+// of consecutive lanes touch consecutive entries), its bits in the order
+// 8..11, 4..7, 0..3; the results end in vec[padx(x)] as above.
+template <class P>
+__device__ __forceinline__ void dense_zeta_down12_regsC(typename P::V (&g)[16],
+                                                        typename P::V *vec, uint32_t t) {
+    constexpr int NR = 16;
+    auto zeta4 = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (!((r >> q) & 1)) g[r] = P::add(g[r], g[r | (1 << q)]);
+    };
+    zeta4();                                            // bits 8..11
+#pragma unroll
+    for (int r = 0; r < NR; ++r) vec[padx((r << 8) | t)] = g[r];
+    __syncthreads();
+    const uint32_t tlo = t & 15, thi = t >> 4;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) g[r] = vec[padx((thi << 8) | (r << 4) | tlo)];
+    zeta4();                                            // bits 4..7
+#pragma unroll
+    for (int r = 0; r < NR; ++r) vec[padx((thi << 8) | (r << 4) | tlo)] = g[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) g[r] = vec[padx((t << 4) | r)];
+    zeta4();                                            // bits 0..3
+#pragma unroll
+    for (int r = 0; r < NR; ++r) vec[padx((t << 4) | r)] = g[r];
+    __syncthreads();
+}
+
 template <class P>
 __device__ __forceinline__ void dense_zeta_down12(const typename P::V *__restrict__ src,
                                                   uint32_t stride, typename P::V *vec,
@@ -2673,7 +2706,8 @@ __device__ __forceinline__ void dense_zeta_down12(const typename P::V *__restric
 
 // The FP32-scaled form of the dense 12-bit passes over the grouped ranks of
 // Y1: a workgroup loads the four ranks of a group at once (32 bytes per
-// entry, each byte read once) and runs the zeta for each in turn; the ranks
+// entry, each byte read once, consecutive lanes on consecutive entries) and
+// runs the zeta for each in turn; the ranks
 // past the groups take one workgroup each. item: the workgroup's index within
 // endpoint v; the grouped items come first, (group, Ht) with Ht fastest.
 // Calls out(s, Ht) after the zeta of rank s has left vec (ends with a barrier).
@@ -2686,11 +2720,11 @@ __device__ __forceinline__ void dense_zeta_down12_x4(const X32 *__restrict__ Y1v
     if (item < G) {
         const uint32_t s0 = (item >> hB) << 2, Ht = item & hmask;
         const uint4 *src = reinterpret_cast<const uint4 *>(Y1v + y1_at(s0, (uint64_t)Ht << 12, hv, kg4));
-        uint4 raw[16][2];                     // entry (t << 4) | r: ranks s0, s0 + 1 | s0 + 2, s0 + 3
+        uint4 raw[16][2];                     // entry r * 256 + t: ranks s0, s0 + 1 | s0 + 2, s0 + 3
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            raw[r][0] = src[2 * ((t << 4) | r)];
-            raw[r][1] = src[2 * ((t << 4) | r) + 1];
+            raw[r][0] = src[2 * ((r << 8) | t)];
+            raw[r][1] = src[2 * ((r << 8) | t) + 1];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -2701,14 +2735,18 @@ __device__ __forceinline__ void dense_zeta_down12_x4(const X32 *__restrict__ Y1v
                 g[r] = (q & 1) ? X32{__uint_as_float(w.z), (int)w.w}
                                : X32{__uint_as_float(w.x), (int)w.y};
             }
-            dense_zeta_down12_regs<PolX32>(g, vec, t);
+            dense_zeta_down12_regsC<PolX32>(g, vec, t);
             out(s0 + q, Ht);
             __syncthreads();                  // vec is read by out()
         }
     } else {
         const uint32_t x = item - G;
         const uint32_t s = kg4 + (x >> hB), Ht = x & hmask;
-        dense_zeta_down12<PolX32>(Y1v + y1_at(s, (uint64_t)Ht << 12, hv, kg4), 1u, vec, t);
+        const X32 *src = Y1v + y1_at(s, (uint64_t)Ht << 12, hv, kg4);
+        X32 g[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) g[r] = src[(r << 8) | t];
+        dense_zeta_down12_regsC<PolX32>(g, vec, t);
         out(s, Ht);
     }
 }
@@ -2798,7 +2836,7 @@ k_gamma_highA12_log(int n, int d, uint32_t KA, int force_trunc, GammaGeom gg, Ta
 
 // Level A for a = 12, FP32-scaled form: the outputs of k_gamma_highA from
 // the dense zeta, over groups of ranks.
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_gamma_highA12(int n, uint32_t KA, GammaGeom gg, Tables tb, const X32 *__restrict__ Y1,
                    X32 *__restrict__ Y2) {
     extern __shared__ unsigned char smem[];
@@ -2816,7 +2854,7 @@ k_gamma_highA12(int n, uint32_t KA, GammaGeom gg, Tables tb, const X32 *__restri
 
 // One level with hv = 12 (every one-level endpoint when n = 25), FP32-scaled
 // form: the outputs of k_gamma_high1 from the dense zeta, over groups of ranks.
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_gamma_high1_12(int n, int d, uint32_t K, GammaGeom gg, Tables tb,
                     const X32 *__restrict__ Y1, X32 *__restrict__ gam) {
     extern __shared__ unsigned char smem[];
