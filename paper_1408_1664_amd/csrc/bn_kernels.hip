@@ -3118,9 +3118,34 @@ __global__ void k_pack2(int n, int m, int W, const uint8_t *__restrict__ data,
     bits[((size_t)j * 2 + 0) * W + w] = zero;
 }
 
+// One step of count_cells2's butterfly, at lane bit B.
+template <int KP, int B>
+__device__ inline void count_scatter(uint32_t *cnt, int lane) {
+    constexpr int sft = 1 << B;
+    if constexpr (B >= KP) {
+#pragma unroll
+        for (int c = 0; c < (2 << KP); ++c) cnt[c] += __shfl_xor(cnt[c], sft, 16);
+    } else {
+        // held: the 2^(B+1) configurations agreeing with the lane above bit
+        // B, counts at 2 * (configuration mod 2^(B+1)) + v
+        constexpr int half = 2 << B;
+        const bool up = (lane >> B) & 1;
+#pragma unroll
+        for (int c = 0; c < half; ++c) {
+            const uint32_t keep = up ? cnt[c + half] : cnt[c];
+            const uint32_t send = up ? cnt[c] : cnt[c + half];
+            cnt[c] = keep + __shfl_xor(send, sft, 16);
+        }
+    }
+}
+
 // Counts of one family of k parents over words w = lane, lane + 16, ...:
 // cell (c << 1) | v, c the parents' values as bits, v the child's value, is
-// the popcount of the AND of the matching planes.
+// the popcount of the AND of the matching planes. The 16 lanes' partial
+// counts are then summed and scattered by a butterfly that, at lane bit b,
+// halves the configurations a lane keeps by configuration bit b (b < k), or
+// sums all it holds (b >= k): lane L < 2^k ends with the two counts of
+// configuration L in cnt[0] and cnt[1].
 template <int KP>
 __device__ inline void count_cells2(const uint32_t *__restrict__ bits, int W, int lane,
                                     int child, const int *par, uint32_t *cnt) {
@@ -3147,10 +3172,10 @@ __device__ inline void count_cells2(const uint32_t *__restrict__ bits, int W, in
 #pragma unroll
         for (int c = 0; c < NC; ++c) cnt[c] += __popc(a[c]);
     }
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int sft = 8; sft > 0; sft >>= 1) cnt[c] += __shfl_xor(cnt[c], sft, 16);
+    count_scatter<KP, 3>(cnt, lane);
+    count_scatter<KP, 2>(cnt, lane);
+    count_scatter<KP, 1>(cnt, lane);
+    count_scatter<KP, 0>(cnt, lane);
 }
 
 // Log-gamma tables of the score paths for data whose variables all have
@@ -3171,9 +3196,10 @@ __global__ void k_lgamma_table(int m, int r, int kind, double ess, double *__res
 }
 
 // BDeu / K2 log marginal likelihood of one family from its cell counts
-// (all variables binary: q = 2^k configurations, r = 2 values); the
-// configurations are split over the 16 lanes, partial sums met by a fixed
-// butterfly. The log-gamma values come from the tables of k_lgamma_table.
+// (all variables binary: q = 2^k configurations, r = 2 values); lane L < q
+// takes configuration L (the counts count_cells2 left it), partial sums met
+// by a fixed butterfly. The log-gamma values come from the tables of
+// k_lgamma_table.
 template <int KP>
 __device__ inline double family_score2(const uint32_t *cnt, int lane, const double *lgt,
                                        int m1) {
@@ -3181,10 +3207,8 @@ __device__ inline double family_score2(const uint32_t *cnt, int lane, const doub
     const double *lj = lgt + (2 * KP) * m1, *ljk = lgt + (2 * KP + 1) * m1;
     const double lg_aj = lj[0], lg_ajk = ljk[0];
     double acc = 0.0;
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-        if ((j & 15) != lane) continue;
-        const uint32_t c0 = cnt[2 * j], c1 = cnt[2 * j + 1];
+    if (lane < Q) {
+        const uint32_t c0 = cnt[0], c1 = cnt[1];
         const uint32_t nj = c0 + c1;
         if (nj) {
             double s = lg_aj - lj[nj];
