@@ -399,22 +399,24 @@ __global__ void k_prep(int n, int d, uint32_t K, const uint32_t *binom,
         if (rtG) rtG[0] = 0;
     }
     const int N = n - 1;
+    // cum[k] = K(N, k): the parent sets of rank below it have at most k members
+    __shared__ uint32_t cum[33];
+    if (t <= d && t < 33) cum[t] = Kcount(binom, N, t);
+    __syncthreads();
+    auto size_of = [&](uint32_t r) {
+        int k = 0;
+        while (k < d && r >= cum[k]) ++k;
+        return k;
+    };
     // the row's maximum (every chunk of the row reads the whole row)
     double mx = -__builtin_huge_val();
-    for (uint32_t r = t; r < K; r += kThreads) {
-        int k = 0;
-        uint32_t off = 0;
-        while (k < d && r >= off + C(binom, N, k)) off += C(binom, N, k++);
-        mx = fmax(mx, log_rho[k] + logp[(size_t)i * K + r]);
-    }
+    for (uint32_t r = t; r < K; r += kThreads)
+        mx = fmax(mx, log_rho[size_of(r)] + logp[(size_t)i * K + r]);
     mx = block_reduce(mx, red, [](double a, double b) { return fmax(a, b); });
     const double E = (gauge && mx > -1e300) ? rint(mx * 1.4426950408889634074) : 0.0;
     const uint32_t r1 = min(K, (chunk + 1) * kPrepChunk);
     for (uint32_t r = chunk * kPrepChunk + t; r < r1; r += kThreads) {
-        int k = 0;
-        uint32_t off = 0;
-        while (k < d && r >= off + C(binom, N, k)) off += C(binom, N, k++);
-        double lb = log_rho[k] + logp[(size_t)i * K + r];
+        const double lb = log_rho[size_of(r)] + logp[(size_t)i * K + r];
         beta[(size_t)i * K + r] = P::from_log(lb - E * 0.69314718055994530942);
     }
     if (chunk == 0 && t == 0) gauge_exp[i] = E;
