@@ -3044,18 +3044,22 @@ __global__ void k_finalize(int n, typename P::Store L, typename P::Store R,
                            const unsigned long long *__restrict__ cnt,
                            const uint32_t *__restrict__ fbA, const uint32_t *__restrict__ fbG,
                            double *__restrict__ diag) {
-    if (threadIdx.x != 0) return;
     using V = typename P::V;
+    const int t = threadIdx.x;
     const V LV = P::load(L, (1ull << n) - 1);
+    // lane k sums layer k's chunks in order; the largest deviation over the
+    // wave (one wave of 64 lanes, n + 1 <= 32 layers)
+    double rl = 0.0;
+    if (t <= n) {
+        V lk = layer[t * kInvChunks];
+        for (int c = 1; c < kInvChunks; ++c) lk = P::add(lk, layer[t * kInvChunks + c]);
+        rl = fabs(P::log_ratio(lk, LV));
+    }
+    for (int o = 32; o > 0; o >>= 1) rl = fmax(rl, __shfl_xor(rl, o));
+    if (t != 0) return;
     double g = 0.0;
     for (int k = 0; k < 2 * n; ++k) g += gauge_exp[k];
     const double rLR = fabs(P::log_ratio(P::load(R, 0), LV));
-    double rl = 0.0;
-    for (int k = 0; k <= n; ++k) {
-        V lk = layer[k * kInvChunks];
-        for (int c = 1; c < kInvChunks; ++c) lk = P::add(lk, layer[k * kInvChunks + c]);
-        rl = fmax(rl, fabs(P::log_ratio(lk, LV)));
-    }
     double re = 0.0;
     for (int v = 0; v < n; ++v) re = fmax(re, resid[v]);
     diag[0] = P::to_log(LV) + g * 0.69314718055994530942;
