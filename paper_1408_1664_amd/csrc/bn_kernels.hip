@@ -945,7 +945,8 @@ __device__ inline uint32_t padx(uint32_t x) { return x + (x >> 4); }
 // F for seed g and G_lo = u * 16 + r in 16 registers (bits 0..3), then, after
 // an LDS transpose, bits 4..b-1. Score ranks are size, then colex: the part
 // of G_hi (with the size offset) comes from a table built per workgroup,
-// hiP[m][j] for the j-th subset of Hh and m smaller elements.
+// hiP[m][j] for the j-th subset of Hh and m smaller elements. Workgroup
+// (i, Hh, y) takes every gridDim.y-th chunk from chunk y.
 template <class P>
 __global__ void __launch_bounds__(kThreads)
 k_alpha_seeds_blk(int n, int d, uint32_t K, uint32_t KS, int b, uint32_t nhiMax, Tables tb,
@@ -994,7 +995,8 @@ k_alpha_seeds_blk(int n, int d, uint32_t K, uint32_t KS, int b, uint32_t nhiMax,
     const uint32_t nu = 1u << (b - 4);                 // thread values of G_lo bits 4..b-1
     const uint64_t tile0 = (uint64_t)blockIdx.x << b;  // tile index (i, Hh, Hl = 0)
     const uint32_t nent = 16u << b;
-    for (uint32_t c0 = 0; c0 < KS; c0 += 16) {
+    // chunks of 16 seed ranks, split over gridDim.y workgroups of the same tiles
+    for (uint32_t c0 = 16 * blockIdx.y; c0 < KS; c0 += 16 * gridDim.y) {
         const uint32_t rk = c0 + g;
         double v[16];
 #pragma unroll
@@ -3439,8 +3441,12 @@ hipError_t launch_lattice(const LatticeArgs &a, const typename P::Store &alpha,
             const uint32_t nhiMax = bS >= 4 ? host_kcount(hA - bS, d) : 0u;
             if (a.KS > 0 && bS >= 4 && d <= 7 && (size_t)(d + 1) * nhiMax <= 4096) {
                 const size_t smB = 8 * (4096 + 256) + 33 * 33 * 4 + (size_t)(d + 1) * nhiMax * 4;
+                // few blocks of tiles (n < 26): their chunks of seed ranks
+                // spread over more workgroups
+                const unsigned nbS = (unsigned)(n << (hA - bS));
+                const unsigned ySplit = std::min((a.KS + 15) / 16, std::max(1u, 2048u / nbS));
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_alpha_seeds_blk<P>),
-                                   dim3((unsigned)(n << (hA - bS))), dim3(kThreads), smB, st, n,
+                                   dim3(nbS, ySplit), dim3(kThreads), smB, st, n,
                                    d, a.K, a.KS, bS, nhiMax, tb, (const double *)a.betal,
                                    (const int *)a.linok, a.Zs);
             } else if (a.KS > 0) {
